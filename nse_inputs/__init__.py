@@ -1,0 +1,124 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the GPU path.
+
+This module holds the workload recipes only (random draws, spectral shapes and
+the coefficient storage order). It holds none of the method's arithmetic: no
+quadrature, no Legendre functions, no transforms, no time stepping.
+
+Storage order of one member's coefficients (complex128, m >= 0 only):
+    index(l, m) = m*(2N+3-m)/2 + (l-m),   0 <= m <= l <= N,
+i.e. m-major, l fastest. The slot (l=0, m=0) is always 0 (the divergence-free
+space starts at degree 1). A real velocity field needs
+alpha[l,-m] = (-1)^m conj(alpha[l,m]), so negative orders are not stored and the
+imaginary part of every m = 0 coefficient is 0.
+
+Spectral recipe (the workloads of the paper's experiments are synthetic
+band-limited spectra, Section 5): a stream-function coefficient
+    psi[l,m] = scale * x * (l(l+1))^(-1.5) * exp(-l/8)
+with x ~ N(0,1) for m = 0 and x = (z1 + i z2)/sqrt(2), z ~ N(0,1) for m > 0,
+drawn from numpy.random.default_rng(seed) in storage order. The state
+coefficient of the divergence-free basis is alpha = sqrt(l(l+1)) * psi, because
+Z[l,m] = (l(l+1))^(-1/2) Curl Y[l,m] and u = Curl psi.
+
+Seeds used by the tests and the benchmark:
+    1 initial state, 2 forcing (scale 1e-2), 3 target state, 4 finite-difference
+    directions, 5 ensemble viscosities, 100+i ensemble member i.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_INITIAL = 1
+SEED_FORCING = 2
+SEED_TARGET = 3
+SEED_DIRECTIONS = 4
+SEED_ENSEMBLE_NU = 5
+SEED_MEMBER0 = 100
+
+
+def coeff_count(N: int) -> int:
+    """Complex slots per member: (N+1)(N+2)/2."""
+    return (N + 1) * (N + 2) // 2
+
+
+def index(N: int, l: int, m: int) -> int:
+    """Storage slot of (l, m), 0 <= m <= l <= N."""
+    if not (0 <= m <= l <= N):
+        raise ValueError(f"(l={l}, m={m}) outside 0 <= m <= l <= {N}")
+    return m * (2 * N + 3 - m) // 2 + (l - m)
+
+
+def degrees_orders(N: int):
+    """Arrays (l, m) of length coeff_count(N) in storage order."""
+    ls, ms = [], []
+    for m in range(N + 1):
+        for l in range(m, N + 1):
+            ls.append(l)
+            ms.append(m)
+    return np.array(ls, dtype=np.int64), np.array(ms, dtype=np.int64)
+
+
+def spectrum(seed: int, N: int, scale: float = 1.0, efold: float = 8.0) -> np.ndarray:
+    """State coefficients alpha (complex128, storage order) of the seeded spectrum."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(coeff_count(N), dtype=np.complex128)
+    k = 0
+    for m in range(N + 1):
+        for l in range(m, N + 1):
+            if l == 0:
+                k += 1
+                continue
+            if m == 0:
+                x = complex(rng.standard_normal(), 0.0)
+            else:
+                z1, z2 = rng.standard_normal(2)
+                x = complex(z1, z2) / np.sqrt(2.0)
+            lam = float(l * (l + 1))
+            psi = scale * x * lam ** -1.5 * np.exp(-l / efold)
+            out[k] = np.sqrt(lam) * psi
+            k += 1
+    return out
+
+
+def initial_state(N: int) -> np.ndarray:
+    return spectrum(SEED_INITIAL, N, 1.0)
+
+
+def forcing(N: int) -> np.ndarray:
+    return spectrum(SEED_FORCING, N, 1e-2)
+
+
+def target_state(N: int) -> np.ndarray:
+    return spectrum(SEED_TARGET, N, 1.0)
+
+
+def directions(N: int, count: int) -> np.ndarray:
+    """count seeded directions of the same spectral shape, shape [count, slots]."""
+    return np.stack([spectrum(SEED_DIRECTIONS * 1000 + i, N, 1.0) for i in range(count)])
+
+
+def ensemble_viscosities(count: int, lo: float = 1e-5, hi: float = 1e-3) -> np.ndarray:
+    """nu_i log-uniform in [lo, hi]."""
+    rng = np.random.default_rng(SEED_ENSEMBLE_NU)
+    return 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=count)
+
+
+def member_state(i: int, N: int) -> np.ndarray:
+    return spectrum(SEED_MEMBER0 + i, N, 1.0)
+
+
+def ensemble_truncations():
+    """The mixed-truncation ensemble: 24 x N=63, 24 x N=127, 16 x N=255."""
+    return [63] * 24 + [127] * 24 + [255] * 16
+
+
+def single_mode(N: int, modes) -> np.ndarray:
+    """A state with the given {(l, m): value} entries and zeros elsewhere."""
+    out = np.zeros(coeff_count(N), dtype=np.complex128)
+    for (l, m), v in modes.items():
+        out[index(N, l, m)] = v
+    return out
+
+
+def as_real_view(alpha: np.ndarray) -> np.ndarray:
+    """Interleaved (re, im) float64 view of a complex128 array."""
+    return np.ascontiguousarray(alpha).view(np.float64)
