@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: NDF2 time steps of the Navier-Stokes equations on
+the rotating sphere at T255 (N = 255, 384 x 768 Gauss-rectangle grid) in FP64 on
+one MI355X.
+
+One step = one full evaluation of the nonlinear term (Legendre synthesis of
+four fields, longitude FFTs + grid product + forward FFT, weighted Legendre
+analysis) fused with the implicit viscous update and the history rotation.
+
+Prints one JSON line. `value` is steps/s with all inputs resident in HBM; the
+per-kernel roofline figure comes from HIP events recorded around every launch
+on the library's stream during a separate instrumented pass of the same steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NSE steps/sec at T255 & T511: FP64 vs split-BF16 (err vs FP64); adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = {
+    "synthesis": "paper_1009_3308_amd/csrc/synthesis.hip",
+    "ring": "paper_1009_3308_amd/csrc/ring_fft.hip",
+    "analysis": "paper_1009_3308_amd/csrc/analysis.hip",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def table_bytes(N, nh, lmax_extra):
+    """Algorithmic bytes of one FP64 Legendre-table pass over l = m..N+lmax_extra."""
+    rows = sum(N + 1 + lmax_extra - m for m in range(N + 1))
+    return 8 * rows * nh
+
+
+def algorithmic_bytes(N, nlat, order, nsrc):
+    """HBM bytes each kernel must move per launch (one member)."""
+    nh = (nlat + 1) // 2
+    slots = (N + 1) * (N + 2) // 2
+    F = 4 * nlat * (N + 1) * 16
+    W = (N + 1) * 2 * nh * 16
+    return {
+        "synthesis": table_bytes(N, nh, 1) + nsrc * slots * 16 + F,
+        "ring": F + W,
+        "analysis": table_bytes(N, nh, 0) + W + (2 * (order + 1) + 1) * slots * 16,
+    }
+
+
+def source_sha(kernel):
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counters, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            entries = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for e in entries:
+        if e.get("kernel") == kernel and e.get("workload") == workload:
+            if e.get("source_sha256") != source_sha(kernel):
+                return None
+            return e.get("bytes_per_launch")
+    return None
+
+
+def run_steps(sph, hist, f, step0, n):
+    sph.step(hist, f, step0, n)
+
+
+def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True):
+    import nse_inputs as I
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sph = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, order=2, graph=graph,
+                         stream=stream)
+        hist = sph.new_history()
+        hist[0] = pkg.to_device(I.initial_state(N))
+        f = pkg.to_device(I.forcing(N))
+        run_steps(sph, hist, f, 0, warmup)
+        sph.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        run_steps(sph, hist, f, warmup, steps)
+        ev1.record(stream)
+        sph.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = ev0.elapsed_time(ev1)
+        finite = bool(torch.isfinite(torch.view_as_real(hist[0])).all())
+    return sph, hist, f, stream, wall, ev_ms, finite
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="bound on the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-t511", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
+              "single-GPU build and multi-GPU sharding is design-only.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import nse_inputs as I
+    import paper_1009_3308_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1009_3308_amd import build
+        build.build()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    N, nu = 255, 1e-5
+    log(f"bench: T255 FP64 warmup={args.warmup} steps={args.steps}")
+    sph, hist, f, stream, wall, ev_ms, finite = time_gpu(pkg, torch, N, nu, args.steps,
+                                                         args.warmup)
+    if not finite:
+        raise RuntimeError("state became non-finite during the timed steps")
+    ms_per_step = 1e3 * wall / args.steps
+    value = args.steps / wall
+    log(f"bench: {value:.1f} steps/s ({ms_per_step * 1e3:.1f} us/step, events {ev_ms:.3f} ms)")
+
+    # per-kernel durations: instrumented eager pass of the same steps
+    nlat = sph.nlat[0]
+    with torch.cuda.stream(stream):
+        sph.profile(True)
+        run_steps(sph, hist, f, args.warmup + args.steps, args.profile_steps)
+        prof = sph.profile_read()
+        sph.profile(False)
+    per_kernel = {k: (ms / n if n else float("nan")) for k, (n, ms) in prof.items()}
+    abytes = algorithmic_bytes(N, nlat, 2, 3)
+    dominant = max(per_kernel, key=lambda k: per_kernel[k])
+    dur_s = per_kernel[dominant] * 1e-3
+    achieved = abytes[dominant] / dur_s / 1e9
+    workload = f"T255 FP64 NDF2 step, N={N}, {nlat}x{2 * nlat}"
+    traffic = measured_traffic(dominant, workload)
+    kernels = {k: {"avg_us": round(per_kernel[k] * 1e3, 2),
+                   "algorithmic_MB": round(abytes[k] / 1e6, 3),
+                   "GBps": round(abytes[k] / (per_kernel[k] * 1e-3) / 1e9, 1)} for k in per_kernel}
+    log(f"bench: kernels {kernels}")
+
+    # one nonlinear evaluation against the oracle (parity spot check at full size)
+    from oracle import nse_oracle as O
+    a0 = I.initial_state(N)
+    with torch.cuda.stream(stream):
+        n_gpu = sph.nonlinear(pkg.to_device(a0))
+        sph.sync()
+    n_gpu = n_gpu.cpu().numpy()
+    S = O.Sphere(N, nlat)
+    n_ref = S.nonlinear(O.to_tensor(a0), 2 * math.pi).numpy()
+    err = float(np.linalg.norm(n_gpu - n_ref) / np.linalg.norm(n_ref))
+    log(f"bench: T255 nonlinear rel err vs oracle {err:.3e}")
+    sph.close()
+
+    extra = {"t255_nonlinear_rel_err_vs_oracle": err, "kernels": kernels,
+             "timed_region_event_ms": round(ev_ms, 3)}
+    if not args.no_t511:
+        steps511 = max(20, args.steps // 5)
+        log(f"bench: T511 FP64 steps={steps511}")
+        s5, h5, f5, st5, wall5, _, fin5 = time_gpu(pkg, torch, 511, 1e-5, steps511, 10)
+        extra["t511_fp64_steps_per_s"] = round(steps511 / wall5, 2) if fin5 else None
+        s5.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = torch.get_num_threads()
+        st = O.Stepper(S, nu, 2 * math.pi, 1e-3, order=2)
+        h = [O.to_tensor(a0)] + [torch.zeros_like(O.to_tensor(a0)) for _ in range(2)]
+        fo = O.to_tensor(I.forcing(N))
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            h = st.step(h, fo, k)
+            k += 1
+            el = time.perf_counter() - t0
+            if k >= 2 and (el > args.cpu_seconds or k >= 200):
+                break
+        cpu = {"value": round(k / el, 4), "unit": "steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{k} NDF2 steps of the FP64 oracle at N=255 (384x768), "
+                         f"direct DFT and Legendre sums, {el:.1f} s"}
+        log(f"bench: oracle {cpu['value']} steps/s on {threads} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload + ", nu=1e-5, Omega=2pi, dt=1e-3, seeded spectrum "
+                                          "psi ~ (l(l+1))^-1.5 e^-l/8 and forcing (scale 1e-2)",
+                   "N": N, "nlat": nlat, "nlon": 2 * nlat, "order": 2, "dt": 1e-3, "nu": nu,
+                   "graph": True, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * nse_sphere.h -- C ABI of the MI355X (gfx950) implementation of the
+ * pseudospectral quadrature method for the incompressible Navier-Stokes
+ * equations on the rotating unit sphere (Ganesh, Le Gia, Sloan).
+ *
+ * The problem (Section 4, eqs. (app_weak_form), (app1_weak_form), (ode)):
+ * find u_N(t) = sum_{l=1..N, |m|<=l} alpha[l,m](t) Z[l,m] with
+ *     d alpha/dt = f - nu lambda_l alpha - n(alpha),
+ *     n[l,m] = (B(u_N,u_N) + C u_N, Z[l,m])_M,            lambda_l = l(l+1),
+ * where Z[l,m] = lambda_l^(-1/2) Curl Y[l,m] (eq. (stok_eig)), B is the
+ * advection (eqs. (B), (short_nonlin1)), C the Coriolis operator (eq. (C)) and
+ * (.,.)_M the Gauss-rectangle discrete inner product (eqs. (quadrule),
+ * (disc_ip)) on nlat = M/2 Gauss-Legendre latitudes x M equispaced longitudes.
+ *
+ * Coefficient storage (every "state" array below):
+ *   complex128, interleaved (re, im) doubles, one block per member, members in
+ *   the order given to nse_sphere_init. Inside a member of truncation N the
+ *   slot of (l, m), 0 <= m <= l <= N, is  m*(2N+3-m)/2 + (l-m)  (m-major), so a
+ *   member holds nse_coeff_count(N) = (N+1)(N+2)/2 complex values. Negative
+ *   orders are implied by alpha[l,-m] = (-1)^m conj(alpha[l,m]) (real field).
+ *   On input the (0,0) slot and the imaginary parts of m = 0 slots must be 0;
+ *   on output they are 0.
+ *
+ * Memory and streams:
+ *   Every array argument of a compute call is a DEVICE pointer (e.g. a torch
+ *   tensor's data_ptr) owned by the caller, which keeps it alive until the work
+ *   enqueued on the context's stream has completed. The library owns its
+ *   tables and workspaces from nse_sphere_init to nse_sphere_destroy and never
+ *   frees caller memory. All work is enqueued on the context's HIP stream;
+ *   calls return before the GPU finishes (use nse_sync or the stream).
+ *
+ * Errors:
+ *   Argument checks are synchronous: on failure a call returns NSE_ERR_ARG (or
+ *   NSE_ERR_UNSUPPORTED), enqueues nothing and records a message readable with
+ *   nse_last_error. HIP failures return NSE_ERR_HIP from the call that observes
+ *   them (launch errors) or from nse_sync (asynchronous errors). A context is
+ *   not thread-safe; separate contexts are independent.
+ */
+#ifndef NSE_SPHERE_H
+#define NSE_SPHERE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nse_ctx nse_ctx; /* opaque, library-owned */
+
+typedef enum {
+  NSE_OK = 0,
+  NSE_ERR_ARG = 1,         /* invalid argument; nothing enqueued              */
+  NSE_ERR_ALLOC = 2,       /* device or host allocation failed                */
+  NSE_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed      */
+  NSE_ERR_UNSUPPORTED = 4, /* valid request this build does not implement     */
+  NSE_ERR_NONFINITE = 5,   /* NaN/Inf detected (NSE_FLAG_CHECK_FINITE)        */
+  NSE_ERR_STATE = 6        /* call not valid in the context's current state   */
+} nse_status;
+
+/* Precision of the Legendre contractions (a8/a2 of the hot path). The Legendre
+ * recurrences, quadrature weights, FFTs, grid products and the viscous update
+ * always run in FP64. */
+enum {
+  NSE_PREC_FP64 = 0,  /* FP64 table, FP64 accumulation                         */
+  NSE_PREC_FP32 = 1,  /* FP32 table and operands, FP32 accumulation            */
+  NSE_PREC_BF16X3 = 2 /* operands split into three bf16 pieces, MFMA, FP32 acc */
+};
+
+enum {
+  NSE_FLAG_GRAPH = 1,       /* replay nse_step through a captured hipGraph      */
+  NSE_FLAG_CHECK_FINITE = 4 /* flag NaN/Inf in the state; nse_sync reports it   */
+};
+
+/* One ensemble member: truncation N >= 1, latitudes nlat (0 = the smallest nlat
+ * with M = 2 nlat >= 3N + 2, eq. (M_choice), whose M factors into 2, 3 and 5),
+ * viscosity nu >= 0. */
+typedef struct {
+  int32_t N;
+  int32_t nlat;
+  double nu;
+} nse_member;
+
+/* Shared parameters: rotation Omega (eq. (C)), step h, NDF order p in 1..5 of
+ * eq. (ode_disc) (kappa_p as printed in Section 4.2), fixed-point sweeps of
+ * the implicit step (1 = nonlinear term at the extrapolated predictor), the
+ * contraction precision and NSE_FLAG_* flags. */
+typedef struct {
+  double omega;
+  double dt;
+  int32_t order;
+  int32_t newton_iters;
+  int32_t precision;
+  uint32_t flags;
+} nse_params;
+
+/* Creates a context: computes the Gauss-Legendre rule (eq. (quadrule)) on the
+ * host, the normalised Legendre tables Pbar[l,m](mu_p), l <= N+1, in FP64 on
+ * the GPU (eq. (sph_har)), FFT twiddles and workspaces. `hip_stream` is a
+ * hipStream_t (NULL = default stream). Returns NSE_ERR_ARG for n_members < 1,
+ * N < 1, 2*nlat < 3N+2, nu < 0, order outside 1..5, newton_iters < 1, an
+ * unknown precision or flag; NSE_ERR_UNSUPPORTED for a grid whose M has a prime
+ * factor other than 2, 3, 5 or M > 2048. *out is NULL on failure. */
+nse_status nse_sphere_init(const nse_member* members, int32_t n_members,
+                           const nse_params* params, void* hip_stream,
+                           nse_ctx** out);
+
+/* Waits for the context's stream, frees everything it owns. NULL is a no-op. */
+nse_status nse_sphere_destroy(nse_ctx* ctx);
+
+/* Rebinds the context to another hipStream_t (captured graphs are dropped). */
+nse_status nse_set_stream(nse_ctx* ctx, void* hip_stream);
+
+/* (N+1)(N+2)/2, or -1 for N < 0. */
+int64_t nse_coeff_count(int32_t N);
+
+/* Complex slots of one full state (sum over members), -1 for NULL. */
+int64_t nse_state_count(const nse_ctx* ctx);
+
+/* Grid of member `member`: writes nlat (and M = 2 nlat) through the int
+ * pointers and, if non-NULL, the nodes mu_p (descending, north first) and
+ * weights w_p into HOST arrays of nlat doubles. */
+nse_status nse_member_grid(const nse_ctx* ctx, int32_t member, int32_t* nlat,
+                           double* mu_host, double* w_host);
+
+/* n = (B(u,u) + C u, Z[l,m])_M for every member (eqs. (app1_weak_form),
+ * (Coriolis_ZLm), (eval_nonlin)), computed by synthesis onto the grid
+ * (Legendre contraction per order m, inverse real FFT per latitude), the
+ * product u . Grad(zeta + 2 Omega cos theta) on the grid, and quadrature
+ * analysis (forward FFT, weighted Legendre contraction).
+ * alpha, n_out: device state arrays (may not alias). */
+nse_status nse_nonlinear(nse_ctx* ctx, const double* alpha, double* n_out);
+
+/* Advances `nsteps` steps of the NDF_p formula (eq. (ode_disc)) with the
+ * nonlinear term at the predictor and the Stokes term nu lambda_l (eq.
+ * (stok_eig)) implicit and diagonal. hist: device array [order+1][state]
+ * (hist[0] = newest state, hist[j] = the state j steps earlier), updated in
+ * place and rotated. forcing: device state array of f[l,m] = (f, Z[l,m])_M,
+ * constant over the call, or NULL for f = 0. step0: global index of the first
+ * step (0 = the first step of the run); steps k < order+1 use the reduced
+ * start-up order q = min(p, k+1). */
+nse_status nse_step(nse_ctx* ctx, double* hist, const double* forcing,
+                    int64_t step0, int32_t nsteps);
+
+/* Vector-Jacobian product of nse_nonlinear at alpha: alpha_bar = J^T n_bar,
+ * J the Jacobian of the real map (re, im) -> (re, im) on the stored doubles.
+ * Device state arrays; alpha_bar is overwritten. */
+nse_status nse_nonlinear_adjoint(nse_ctx* ctx, const double* alpha,
+                                 const double* n_bar, double* alpha_bar);
+
+/* Adjoint of one nse_step call with nsteps = 1 at global step index `step`:
+ * hist is the history BEFORE that step ([order+1][state], device), hist_bar
+ * holds dL/d(history after the step) on input and dL/d(history before the
+ * step) on output (device, [order+1][state]). The forcing is not
+ * differentiated. Requires newton_iters == 1. */
+nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist,
+                            const double* forcing, int64_t step,
+                            double* hist_bar);
+
+/* Grid values of u_theta, u_phi and zeta for every member: device array
+ * [member][3][nlat][M] of doubles (latitudes north to south, longitudes
+ * phi_j = 2 pi j / M). */
+nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out);
+
+/* Normalised Legendre values of one member's table: writes Pbar[l,m](mu_p)
+ * for l = m..N+1 and the nlat/2 northern nodes p as a device array
+ * [l-m][p] of doubles. For testing the FP64 table. */
+nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m,
+                               double* out);
+
+/* Kernels of the hot path, for per-kernel timing. */
+enum {
+  NSE_KERNEL_SYNTHESIS = 0, /* Legendre synthesis of the four grid fields     */
+  NSE_KERNEL_RING = 1,      /* longitude FFTs + grid product + forward FFT    */
+  NSE_KERNEL_ANALYSIS = 2,  /* weighted Legendre analysis (+ step update)     */
+  NSE_KERNEL_KINDS = 3
+};
+
+/* Per-kernel timing. While enabled, every kernel launch of the context is
+ * bracketed by HIP events on the context stream and nse_step does not replay
+ * graphs. nse_profile_read waits for the stream and returns, for kernel kind
+ * `kind`, the launches and their summed duration in milliseconds since the
+ * last read or enable; it then resets that kind's counters. */
+nse_status nse_profile_enable(nse_ctx* ctx, int32_t enable);
+nse_status nse_profile_read(nse_ctx* ctx, int32_t kind, int64_t* launches,
+                            double* total_ms);
+
+/* Blocks until the stream is idle; reports asynchronous HIP errors and, with
+ * NSE_FLAG_CHECK_FINITE, NSE_ERR_NONFINITE if a step produced NaN/Inf. */
+nse_status nse_sync(nse_ctx* ctx);
+
+const char* nse_status_string(nse_status s);
+const char* nse_last_error(const nse_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSE_SPHERE_H */

@@ -1,0 +1,296 @@
+"""Python binding of libnse_sphere.so (include/nse_sphere.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library.
+Arrays are torch tensors on the GPU (complex128 states, float64 grids); the
+library enqueues on the torch stream given at construction. If the library is
+not built, every entry point raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnse_sphere.so")
+
+NSE_OK = 0
+NSE_ERR_ARG = 1
+NSE_ERR_ALLOC = 2
+NSE_ERR_HIP = 3
+NSE_ERR_UNSUPPORTED = 4
+NSE_ERR_NONFINITE = 5
+NSE_ERR_STATE = 6
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_BF16X3 = 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
+
+FLAG_GRAPH = 1
+FLAG_CHECK_FINITE = 4
+
+# Every function the header declares (checked against include/nse_sphere.h by the tests).
+EXPORTS = (
+    "nse_sphere_init", "nse_sphere_destroy", "nse_set_stream", "nse_coeff_count",
+    "nse_state_count", "nse_member_grid", "nse_nonlinear", "nse_step",
+    "nse_nonlinear_adjoint", "nse_step_adjoint", "nse_synthesize", "nse_legendre_values",
+    "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
+)
+
+KERNEL_KINDS = {"synthesis": 0, "ring": 1, "analysis": 2}
+
+
+class NseError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class Member(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nlat", ctypes.c_int32), ("nu", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("dt", ctypes.c_double), ("order", ctypes.c_int32),
+                ("newton_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libnse_sphere.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(python -m paper_1009_3308_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32, i64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    st = ctypes.c_int
+    sig = {
+        "nse_sphere_init": (st, [ctypes.POINTER(Member), i32, ctypes.POINTER(Params), vp,
+                                 ctypes.POINTER(vp)]),
+        "nse_sphere_destroy": (st, [vp]),
+        "nse_set_stream": (st, [vp, vp]),
+        "nse_coeff_count": (i64, [i32]),
+        "nse_state_count": (i64, [vp]),
+        "nse_member_grid": (st, [vp, i32, ctypes.POINTER(i32), dp, dp]),
+        "nse_nonlinear": (st, [vp, dp, dp]),
+        "nse_step": (st, [vp, dp, dp, i64, i32]),
+        "nse_nonlinear_adjoint": (st, [vp, dp, dp, dp]),
+        "nse_step_adjoint": (st, [vp, dp, dp, i64, dp]),
+        "nse_synthesize": (st, [vp, dp, dp]),
+        "nse_legendre_values": (st, [vp, i32, i32, dp]),
+        "nse_sync": (st, [vp]),
+        "nse_profile_enable": (st, [vp, i32]),
+        "nse_profile_read": (st, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
+        "nse_status_string": (ctypes.c_char_p, [st]),
+        "nse_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def coeff_count(N: int) -> int:
+    return int(lib().nse_coeff_count(N))
+
+
+def _check(status: int, ctx=None):
+    if status != NSE_OK:
+        L = lib()
+        msg = L.nse_last_error(ctx).decode() if L.nse_last_error(ctx) else ""
+        name = L.nse_status_string(status).decode()
+        raise NseError(status, f"{name}: {msg}")
+
+
+def _ptr(t, dtype, numel=None, name="array"):
+    """Device pointer of a contiguous GPU tensor of the given dtype (None -> NULL)."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sphere:
+    """A context of one or more members (truncation N, latitudes nlat, viscosity nu).
+
+    members: sequence of (N, nlat, nu) with nlat = 0 for the smallest alias-free grid.
+    """
+
+    def __init__(self, members: Sequence[tuple], omega: float, dt: float, order: int = 2,
+                 newton_iters: int = 1, precision: str = "fp64", graph: bool = False,
+                 check_finite: bool = False, stream=None):
+        import torch
+        L = lib()
+        self.member_specs = [(int(N), int(nlat), float(nu)) for (N, nlat, nu) in members]
+        arr = (Member * len(self.member_specs))(*[Member(N, nl, nu) for (N, nl, nu) in
+                                                   self.member_specs])
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_CHECK_FINITE if check_finite else 0)
+        self.params = Params(float(omega), float(dt), int(order), int(newton_iters),
+                             PRECISIONS[precision], flags)
+        self.order = int(order)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = L.nse_sphere_init(arr, len(self.member_specs), ctypes.byref(self.params),
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        _check(st, None)
+        self._h = h
+        self.state_count = int(L.nse_state_count(h))
+        self.offsets, self.nlat = [], []
+        off = 0
+        for i, (N, _, _) in enumerate(self.member_specs):
+            self.offsets.append(off)
+            off += coeff_count(N)
+            nl = ctypes.c_int32()
+            _check(L.nse_member_grid(h, i, ctypes.byref(nl), None, None), h)
+            self.nlat.append(nl.value)
+
+    # -- helpers -------------------------------------------------------------
+    def _handle(self):
+        if self._h is None:
+            raise NseError(NSE_ERR_STATE, "context is closed")
+        return self._h
+
+    def grid(self, member: int = 0):
+        """(mu, w) of a member's Gauss-Legendre rule as float64 numpy arrays."""
+        import numpy as np
+        nl = self.nlat[member]
+        mu = np.zeros(nl)
+        w = np.zeros(nl)
+        _check(lib().nse_member_grid(self._handle(), member, None,
+                                     mu.ctypes.data_as(ctypes.c_void_p),
+                                     w.ctypes.data_as(ctypes.c_void_p)), self._h)
+        return mu, w
+
+    def new_state(self):
+        import torch
+        return torch.zeros(self.state_count, dtype=torch.complex128, device="cuda")
+
+    def new_history(self):
+        import torch
+        return torch.zeros(self.order + 1, self.state_count, dtype=torch.complex128,
+                           device="cuda")
+
+    # -- the hot path ----------------------------------------------------------
+    def nonlinear(self, alpha, out=None):
+        import torch
+        if out is None:
+            out = self.new_state()
+        _check(lib().nse_nonlinear(self._handle(),
+                                   _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+                                   _ptr(out, torch.complex128, self.state_count, "n_out")),
+               self._h)
+        return out
+
+    def step(self, hist, forcing=None, step0: int = 0, nsteps: int = 1):
+        import torch
+        _check(lib().nse_step(self._handle(),
+                              _ptr(hist, torch.complex128, (self.order + 1) * self.state_count,
+                                   "hist"),
+                              _ptr(forcing, torch.complex128, self.state_count, "forcing"),
+                              int(step0), int(nsteps)), self._h)
+        return hist
+
+    def nonlinear_adjoint(self, alpha, n_bar, out=None):
+        import torch
+        if out is None:
+            out = self.new_state()
+        _check(lib().nse_nonlinear_adjoint(
+            self._handle(), _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+            _ptr(n_bar, torch.complex128, self.state_count, "n_bar"),
+            _ptr(out, torch.complex128, self.state_count, "alpha_bar")), self._h)
+        return out
+
+    def step_adjoint(self, hist, forcing, step: int, hist_bar):
+        import torch
+        n = (self.order + 1) * self.state_count
+        _check(lib().nse_step_adjoint(
+            self._handle(), _ptr(hist, torch.complex128, n, "hist"),
+            _ptr(forcing, torch.complex128, self.state_count, "forcing"), int(step),
+            _ptr(hist_bar, torch.complex128, n, "hist_bar")), self._h)
+        return hist_bar
+
+    def synthesize(self, alpha):
+        """[u_theta, u_phi, zeta] grids, one float64 tensor [3, nlat, M] per member."""
+        import torch
+        sizes = [3 * nl * 2 * nl for nl in self.nlat]
+        out = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+        _check(lib().nse_synthesize(self._handle(),
+                                    _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+                                    _ptr(out, torch.float64)), self._h)
+        res, o = [], 0
+        for nl, s in zip(self.nlat, sizes):
+            res.append(out[o:o + s].view(3, nl, 2 * nl))
+            o += s
+        return res
+
+    def legendre_values(self, member: int, m: int):
+        """Pbar[l,m](mu_p), l = m..N+1, northern nodes: float64 tensor [N+2-m, ceil(nlat/2)]."""
+        import torch
+        N = self.member_specs[member][0]
+        nh = (self.nlat[member] + 1) // 2
+        out = torch.empty((N + 2 - m) * nh, dtype=torch.float64, device="cuda")
+        _check(lib().nse_legendre_values(self._handle(), member, m, _ptr(out, torch.float64)),
+               self._h)
+        return out.view(N + 2 - m, nh)
+
+    def profile(self, enable: bool = True):
+        """Starts (or stops) per-kernel event timing on the context stream."""
+        _check(lib().nse_profile_enable(self._handle(), 1 if enable else 0), self._h)
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms)} since the last read; resets the counters."""
+        out = {}
+        for name, kind in KERNEL_KINDS.items():
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _check(lib().nse_profile_read(self._handle(), kind, ctypes.byref(n), ctypes.byref(ms)),
+                   self._h)
+            out[name] = (int(n.value), float(ms.value))
+        return out
+
+    def sync(self):
+        _check(lib().nse_sync(self._handle()), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().nse_sphere_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def member_slice(self, i: int):
+        N = self.member_specs[i][0]
+        return slice(self.offsets[i], self.offsets[i] + coeff_count(N))
+
+
+def to_device(a, device="cuda"):
+    """complex128 GPU tensor from a numpy array."""
+    import torch
+    return torch.as_tensor(a, dtype=torch.complex128).to(device).contiguous()

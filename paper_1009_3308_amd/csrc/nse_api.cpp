@@ -1,0 +1,661 @@
+// C ABI of libnse_sphere.so (declared in include/nse_sphere.h): context
+// lifetime, argument validation, grouping of members by grid, the NDF_p step
+// schedule and the launch sequences of the hot path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nse_sphere.h"
+#include "nse_internal.h"
+
+using namespace nse;
+
+namespace {
+
+struct Group {
+  int N = 0, nlat = 0, nh = 0, M = 0;
+  std::vector<int> members;          // global member indices
+  std::vector<int64_t> offsets;      // complex-slot offsets of those members
+  std::vector<double> nu;
+  std::vector<double> mu, w;         // all nlat nodes (host)
+  FftPlan plan{};
+  double *d_mu = nullptr, *d_w = nullptr, *d_T1 = nullptr, *d_T2 = nullptr;
+  float *d_T1f = nullptr, *d_T2f = nullptr;
+  double2 *d_F = nullptr, *d_W = nullptr, *d_tw = nullptr;
+  int64_t* d_off = nullptr;
+  double* d_nu = nullptr;
+
+  GroupView view() const {
+    GroupView g{};
+    g.N = N;
+    g.nlat = nlat;
+    g.nh = nh;
+    g.M = M;
+    g.nb = (int)members.size();
+    g.mu = d_mu;
+    g.w = d_w;
+    g.T1 = d_T1;
+    g.T2 = d_T2;
+    g.T1f = d_T1f;
+    g.T2f = d_T2f;
+    g.F = d_F;
+    g.W = d_W;
+    g.tw = d_tw;
+    g.off = d_off;
+    g.nu = d_nu;
+    return g;
+  }
+  // View restricted to the i-th member of the group.
+  GroupView member_view(int i) const {
+    GroupView g = view();
+    g.nb = 1;
+    g.F = d_F + (int64_t)i * 4 * nlat * (N + 1);
+    g.W = d_W + (int64_t)i * (N + 1) * 2 * nh;
+    g.off = d_off + i;
+    g.nu = d_nu + i;
+    return g;
+  }
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct nse_ctx {
+  std::vector<nse_member> members;
+  std::vector<int64_t> member_offset;
+  std::vector<int> member_group, member_index;  // group and index within it
+  nse_params params{};
+  hipStream_t stream = nullptr;
+  std::vector<Group> groups;
+  int64_t state_count = 0;
+  double2* d_iter = nullptr;
+  int* d_flag = nullptr;
+  std::string err;
+  // captured step chunks keyed by (hist, forcing, chunk length)
+  std::map<std::tuple<const void*, const void*, int>, GraphEntry> graphs;
+  // per-kernel timing
+  bool profiling = false;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  int64_t prof_count[NSE_KERNEL_KINDS] = {0, 0, 0};
+  double prof_ms[NSE_KERNEL_KINDS] = {0, 0, 0};
+};
+
+namespace {
+
+constexpr int kGraphChunk = 10;
+constexpr double kPi = 3.14159265358979323846;
+
+nse_status fail(nse_ctx* c, nse_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+thread_local std::string g_init_error;
+
+nse_status hip_fail(nse_ctx* c, hipError_t e, const char* what) {
+  return fail(c, NSE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define NSE_HIP(ctx, call)                         \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// kappa_p of the NDF_p formulas (Section 4.2, after eq. (ode_disc)).
+const double kKappa[6] = {0.0, -0.1850, -1.0 / 9.0, -0.0823, -0.0415, 0.0};
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Coefficients of sum_{m=1}^{q} (1/m) nabla^m y_{n+1} - kappa_q gamma_q nabla^{q+1} y_{n+1}
+// (eq. (ode_disc)) as c_0..c_{len-1} of sum_j c_j y_{n+1-j}, and the
+// predictor sum_{j=0}^{d} nabla^j y_n = sum_i pi_i y_{n-i} for step index k:
+// start-up order q = min(p, k+1), kappa only once q+1 past states exist,
+// predictor degree d = min(q, k).
+void step_scheme(int p, int64_t k, std::vector<double>& c, std::vector<double>& pi) {
+  const int q = (int)std::min<int64_t>(p, k + 1);
+  const bool kap = (k >= q) && kKappa[q] != 0.0;
+  const int len = kap ? q + 2 : q + 1;
+  c.assign(len, 0.0);
+  for (int m = 1; m <= q; ++m)
+    for (int j = 0; j <= m; ++j) c[j] += ((j & 1) ? -1.0 : 1.0) * binom(m, j) / m;
+  if (kap) {
+    double gamma = 0.0;
+    for (int j = 1; j <= q; ++j) gamma += 1.0 / j;
+    for (int j = 0; j <= q + 1; ++j)
+      c[j] -= kKappa[q] * gamma * ((j & 1) ? -1.0 : 1.0) * binom(q + 1, j);
+  }
+  const int d = (int)std::min<int64_t>(q, k);
+  pi.assign(d + 1, 0.0);
+  for (int j = 0; j <= d; ++j)
+    for (int i = 0; i <= j; ++i) pi[i] += ((i & 1) ? -1.0 : 1.0) * binom(j, i);
+}
+
+int min_nlat(int N) { return (3 * N + 2 + 1) / 2; }
+
+size_t synth_lds(int N) { return sizeof(double2) * (size_t)((N + 3) + 4 * (N + 2)); }
+
+void free_group(Group& g) {
+  (void)hipFree(g.d_mu);
+  (void)hipFree(g.d_w);
+  (void)hipFree(g.d_T1);
+  (void)hipFree(g.d_T2);
+  (void)hipFree(g.d_T1f);
+  (void)hipFree(g.d_T2f);
+  (void)hipFree(g.d_F);
+  (void)hipFree(g.d_W);
+  (void)hipFree(g.d_tw);
+  (void)hipFree(g.d_off);
+  (void)hipFree(g.d_nu);
+}
+
+void drop_graphs(nse_ctx* c) {
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  c->graphs.clear();
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, sizeof(T) * (count ? count : 1));
+}
+
+nse_status build_group(nse_ctx* c, Group& g) {
+  g.nh = (g.nlat + 1) / 2;
+  g.M = 2 * g.nlat;
+  gauss_legendre(g.nlat, g.mu, g.w);
+  const int nb = (int)g.members.size();
+  NSE_HIP(c, dalloc(&g.d_mu, g.nh));
+  NSE_HIP(c, dalloc(&g.d_w, g.nh));
+  NSE_HIP(c, hipMemcpy(g.d_mu, g.mu.data(), sizeof(double) * g.nh, hipMemcpyHostToDevice));
+  NSE_HIP(c, hipMemcpy(g.d_w, g.w.data(), sizeof(double) * g.nh, hipMemcpyHostToDevice));
+  const int64_t ts = table_size(g.N, g.nh);
+  NSE_HIP(c, dalloc(&g.d_T1, ts));
+  NSE_HIP(c, dalloc(&g.d_T2, ts));
+  if (c->params.precision != NSE_PREC_FP64) {
+    NSE_HIP(c, dalloc(&g.d_T1f, ts));
+    NSE_HIP(c, dalloc(&g.d_T2f, ts));
+  }
+  NSE_HIP(c, dalloc(&g.d_F, (size_t)nb * 4 * g.nlat * (g.N + 1)));
+  NSE_HIP(c, dalloc(&g.d_W, (size_t)nb * (g.N + 1) * 2 * g.nh));
+  std::vector<double2> tw(g.M);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int k = 0; k < g.M; ++k) {
+    const long double a = two_pi * k / g.M;
+    tw[k] = make_double2((double)std::cos(a), (double)-std::sin(a));
+  }
+  NSE_HIP(c, dalloc(&g.d_tw, g.M));
+  NSE_HIP(c, hipMemcpy(g.d_tw, tw.data(), sizeof(double2) * g.M, hipMemcpyHostToDevice));
+  NSE_HIP(c, dalloc(&g.d_off, nb));
+  NSE_HIP(c, dalloc(&g.d_nu, nb));
+  NSE_HIP(c, hipMemcpy(g.d_off, g.offsets.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice));
+  NSE_HIP(c, hipMemcpy(g.d_nu, g.nu.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
+  NSE_HIP(c, launch_legendre_table(g.view(), g.d_T1, g.d_T2, g.d_T1f, g.d_T2f, c->stream));
+  return NSE_OK;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+hipError_t take_event(nse_ctx* c, hipEvent_t* e) {
+  if (!c->event_pool.empty()) {
+    *e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Resolves recorded event pairs into the per-kind totals.
+nse_status collect_profile(nse_ctx* c) {
+  NSE_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    NSE_HIP(c, hipEventElapsedTime(&ms, p.a, p.b));
+    c->prof_count[p.kind] += 1;
+    c->prof_ms[p.kind] += ms;
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return NSE_OK;
+}
+
+// Runs one launcher, bracketed by events when profiling.
+template <typename F>
+nse_status timed_launch(nse_ctx* c, int kind, F&& launch) {
+  if (!c->profiling) {
+    NSE_HIP(c, launch());
+    return NSE_OK;
+  }
+  nse_ctx::Pending p{kind, nullptr, nullptr};
+  NSE_HIP(c, take_event(c, &p.a));
+  NSE_HIP(c, take_event(c, &p.b));
+  NSE_HIP(c, hipEventRecord(p.a, c->stream));
+  NSE_HIP(c, launch());
+  NSE_HIP(c, hipEventRecord(p.b, c->stream));
+  c->pending.push_back(p);
+  if (c->pending.size() > 4096) return collect_profile(c);
+  return NSE_OK;
+}
+
+// Enqueues one full evaluation chain (synthesis, ring, analysis) for every group.
+nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out) {
+  for (auto& g : c->groups) {
+    const GroupView v = g.view();
+    nse_status s;
+    s = timed_launch(c, NSE_KERNEL_SYNTHESIS,
+                     [&] { return launch_synthesis(v, in, SYNTH_NONLINEAR, c->stream); });
+    if (s != NSE_OK) return s;
+    s = timed_launch(c, NSE_KERNEL_RING,
+                     [&] { return launch_ring(v, g.plan, SYNTH_NONLINEAR, nullptr, c->stream); });
+    if (s != NSE_OK) return s;
+    s = timed_launch(c, NSE_KERNEL_ANALYSIS, [&] { return launch_analysis(v, out, c->stream); });
+    if (s != NSE_OK) return s;
+  }
+  return NSE_OK;
+}
+
+// Enqueues step k (all fixed-point sweeps) on the context stream.
+nse_status enqueue_step(nse_ctx* c, double2* hist, const double2* forcing, int64_t k) {
+  std::vector<double> cc, pi;
+  step_scheme(c->params.order, k, cc, pi);
+  const int K = c->params.newton_iters;
+  for (int it = 0; it < K; ++it) {
+    SynthInput in{};
+    in.coriolis = 2.0 * c->params.omega * std::sqrt(4.0 * kPi / 3.0);
+    if (it == 0) {
+      in.nsrc = (int)pi.size();
+      for (int i = 0; i < in.nsrc; ++i) {
+        in.src[i] = hist + (int64_t)i * c->state_count;
+        in.coef[i] = pi[i];
+      }
+    } else {
+      in.nsrc = 1;
+      in.src[0] = c->d_iter;
+      in.coef[0] = 1.0;
+    }
+    AnalOutput out{};
+    out.mode = (it == K - 1) ? ANAL_STEP_FINAL : ANAL_STEP_ITER;
+    out.hist = hist;
+    out.state_count = c->state_count;
+    out.depth = c->params.order + 1;
+    out.ncoef = (int)cc.size();
+    for (int j = 0; j < out.ncoef; ++j) out.c[j] = cc[j];
+    out.h = c->params.dt;
+    out.forcing = forcing;
+    out.iter = c->d_iter;
+    out.nonfinite = (c->params.flags & NSE_FLAG_CHECK_FINITE) ? c->d_flag : nullptr;
+    nse_status s = enqueue_chain(c, in, out);
+    if (s != NSE_OK) return s;
+  }
+  return NSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nse_status_string(nse_status s) {
+  switch (s) {
+    case NSE_OK: return "NSE_OK";
+    case NSE_ERR_ARG: return "NSE_ERR_ARG: invalid argument";
+    case NSE_ERR_ALLOC: return "NSE_ERR_ALLOC: allocation failed";
+    case NSE_ERR_HIP: return "NSE_ERR_HIP: HIP runtime error";
+    case NSE_ERR_UNSUPPORTED: return "NSE_ERR_UNSUPPORTED: not supported by this build";
+    case NSE_ERR_NONFINITE: return "NSE_ERR_NONFINITE: NaN or Inf in the state";
+    case NSE_ERR_STATE: return "NSE_ERR_STATE: invalid context state";
+  }
+  return "unknown nse_status";
+}
+
+const char* nse_last_error(const nse_ctx* ctx) {
+  if (!ctx) return g_init_error.c_str();
+  return ctx->err.c_str();
+}
+
+int64_t nse_coeff_count(int32_t N) {
+  if (N < 0) return -1;
+  return (int64_t)(N + 1) * (N + 2) / 2;
+}
+
+int64_t nse_state_count(const nse_ctx* ctx) { return ctx ? ctx->state_count : -1; }
+
+nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const nse_params* params,
+                           void* hip_stream, nse_ctx** out) {
+  g_init_error.clear();
+  auto init_fail = [&](nse_status s, const std::string& msg) {
+    g_init_error = msg;
+    return s;
+  };
+  if (!out) return init_fail(NSE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!members || n_members < 1) return init_fail(NSE_ERR_ARG, "need at least one member");
+  if (!params) return init_fail(NSE_ERR_ARG, "params is NULL");
+  const nse_params& P = *params;
+  if (P.order < 1 || P.order > 5) return init_fail(NSE_ERR_ARG, "order must be 1..5");
+  if (P.newton_iters < 1 || P.newton_iters > 1000)
+    return init_fail(NSE_ERR_ARG, "newton_iters must be 1..1000");
+  if (P.precision != NSE_PREC_FP64 && P.precision != NSE_PREC_FP32 &&
+      P.precision != NSE_PREC_BF16X3)
+    return init_fail(NSE_ERR_ARG, "unknown precision");
+  if (P.flags & ~(uint32_t)(NSE_FLAG_GRAPH | NSE_FLAG_CHECK_FINITE))
+    return init_fail(NSE_ERR_ARG, "unknown flag bits");
+  if (!is_finite(P.omega)) return init_fail(NSE_ERR_ARG, "omega must be finite");
+  if (!is_finite(P.dt) || !(P.dt > 0.0)) return init_fail(NSE_ERR_ARG, "dt must be finite and > 0");
+  if (P.precision != NSE_PREC_FP64)
+    return init_fail(NSE_ERR_UNSUPPORTED, "reduced-precision contractions are not built yet");
+
+  std::vector<nse_member> mem(members, members + n_members);
+  for (int i = 0; i < n_members; ++i) {
+    nse_member& m = mem[i];
+    char buf[256];
+    if (m.N < 1) {
+      snprintf(buf, sizeof buf, "member %d: N must be >= 1", i);
+      return init_fail(NSE_ERR_ARG, buf);
+    }
+    if (!is_finite(m.nu) || m.nu < 0.0) {
+      snprintf(buf, sizeof buf, "member %d: nu must be finite and >= 0", i);
+      return init_fail(NSE_ERR_ARG, buf);
+    }
+    if (m.nlat < 0) {
+      snprintf(buf, sizeof buf, "member %d: nlat must be >= 0", i);
+      return init_fail(NSE_ERR_ARG, buf);
+    }
+    FftPlan plan{};
+    if (m.nlat == 0) {
+      int nl = min_nlat(m.N);
+      while (2 * nl <= kMaxM && !fft_factor(2 * nl, plan)) ++nl;
+      m.nlat = nl;
+    } else if (2 * (int64_t)m.nlat < 3 * (int64_t)m.N + 2) {
+      snprintf(buf, sizeof buf,
+               "member %d: M = 2*nlat = %d < 3N+2 = %d aliases the nonlinear term", i,
+               2 * m.nlat, 3 * m.N + 2);
+      return init_fail(NSE_ERR_ARG, buf);
+    }
+    if (2 * (int64_t)m.nlat > kMaxM || !fft_factor(2 * m.nlat, plan)) {
+      snprintf(buf, sizeof buf,
+               "member %d: M = %d must be <= %d and factor into 2, 3 and 5", i, 2 * m.nlat, kMaxM);
+      return init_fail(NSE_ERR_UNSUPPORTED, buf);
+    }
+    if (synth_lds(m.N) > 65536) {
+      snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,
+               m.N);
+      return init_fail(NSE_ERR_UNSUPPORTED, buf);
+    }
+  }
+
+  std::unique_ptr<nse_ctx> c(new (std::nothrow) nse_ctx);
+  if (!c) return init_fail(NSE_ERR_ALLOC, "host allocation failed");
+  c->members = mem;
+  c->params = P;
+  c->stream = (hipStream_t)hip_stream;
+  c->member_offset.resize(n_members);
+  c->member_group.resize(n_members);
+  c->member_index.resize(n_members);
+  int64_t off = 0;
+  for (int i = 0; i < n_members; ++i) {
+    c->member_offset[i] = off;
+    off += nse_coeff_count(mem[i].N);
+    int gi = -1;
+    for (size_t j = 0; j < c->groups.size(); ++j)
+      if (c->groups[j].N == mem[i].N && c->groups[j].nlat == mem[i].nlat) gi = (int)j;
+    if (gi < 0) {
+      Group g;
+      g.N = mem[i].N;
+      g.nlat = mem[i].nlat;
+      fft_factor(2 * g.nlat, g.plan);
+      c->groups.push_back(g);
+      gi = (int)c->groups.size() - 1;
+    }
+    c->member_group[i] = gi;
+    c->member_index[i] = (int)c->groups[gi].members.size();
+    c->groups[gi].members.push_back(i);
+    c->groups[gi].offsets.push_back(c->member_offset[i]);
+    c->groups[gi].nu.push_back(mem[i].nu);
+  }
+  c->state_count = off;
+
+  auto cleanup = [&](nse_status s) {
+    for (auto& g : c->groups) free_group(g);
+    (void)hipFree(c->d_iter);
+    (void)hipFree(c->d_flag);
+    g_init_error = c->err;
+    return s;
+  };
+  for (auto& g : c->groups) {
+    nse_status s = build_group(c.get(), g);
+    if (s != NSE_OK) return cleanup(s);
+  }
+  hipError_t e = dalloc(&c->d_iter, (size_t)c->state_count);
+  if (e == hipSuccess) e = dalloc(&c->d_flag, 1);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return cleanup(hip_fail(c.get(), e, "init"));
+  *out = c.release();
+  return NSE_OK;
+}
+
+nse_status nse_sphere_destroy(nse_ctx* ctx) {
+  if (!ctx) return NSE_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_graphs(ctx);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto& g : ctx->groups) free_group(g);
+  (void)hipFree(ctx->d_iter);
+  (void)hipFree(ctx->d_flag);
+  delete ctx;
+  return NSE_OK;
+}
+
+nse_status nse_set_stream(nse_ctx* ctx, void* hip_stream) {
+  if (!ctx) return NSE_ERR_ARG;
+  drop_graphs(ctx);
+  ctx->stream = (hipStream_t)hip_stream;
+  return NSE_OK;
+}
+
+nse_status nse_member_grid(const nse_ctx* ctx, int32_t member, int32_t* nlat, double* mu_host,
+                           double* w_host) {
+  if (!ctx) return NSE_ERR_ARG;
+  nse_ctx* c = const_cast<nse_ctx*>(ctx);
+  if (member < 0 || member >= (int)ctx->members.size())
+    return fail(c, NSE_ERR_ARG, "member %d out of range", member);
+  const Group& g = ctx->groups[ctx->member_group[member]];
+  if (nlat) *nlat = g.nlat;
+  if (mu_host) std::memcpy(mu_host, g.mu.data(), sizeof(double) * g.nlat);
+  if (w_host) std::memcpy(w_host, g.w.data(), sizeof(double) * g.nlat);
+  return NSE_OK;
+}
+
+nse_status nse_nonlinear(nse_ctx* ctx, const double* alpha, double* n_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !n_out) return fail(ctx, NSE_ERR_ARG, "alpha and n_out must be non-NULL");
+  if (alpha == n_out) return fail(ctx, NSE_ERR_ARG, "alpha and n_out may not alias");
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = (const double2*)alpha;
+  in.coef[0] = 1.0;
+  in.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  AnalOutput out{};
+  out.mode = ANAL_NONLINEAR;
+  out.n_out = (double2*)n_out;
+  out.state_count = ctx->state_count;
+  return enqueue_chain(ctx, in, out);
+}
+
+nse_status nse_step(nse_ctx* ctx, double* hist, const double* forcing, int64_t step0,
+                    int32_t nsteps) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!hist) return fail(ctx, NSE_ERR_ARG, "hist must be non-NULL");
+  if (step0 < 0) return fail(ctx, NSE_ERR_ARG, "step0 must be >= 0");
+  if (nsteps < 0) return fail(ctx, NSE_ERR_ARG, "nsteps must be >= 0");
+  double2* h = (double2*)hist;
+  const double2* f = (const double2*)forcing;
+  const int p = ctx->params.order;
+  int64_t k = step0;
+  const int64_t end = step0 + nsteps;
+  // start-up steps use their own coefficients; from k = p+1 on the step is fixed
+  for (; k < end && k <= p; ++k) {
+    nse_status s = enqueue_step(ctx, h, f, k);
+    if (s != NSE_OK) return s;
+  }
+  const bool graph =
+      (ctx->params.flags & NSE_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->profiling;
+  if (graph) {
+    while (end - k >= kGraphChunk) {
+      auto key = std::make_tuple((const void*)hist, (const void*)forcing, kGraphChunk);
+      auto it = ctx->graphs.find(key);
+      if (it == ctx->graphs.end()) {
+        GraphEntry ge;
+        NSE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        nse_status s = NSE_OK;
+        for (int i = 0; i < kGraphChunk && s == NSE_OK; ++i) s = enqueue_step(ctx, h, f, k + i);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
+        if (s != NSE_OK) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return s;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        ge.graph = gr;
+        e = hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          (void)hipGraphDestroy(gr);
+          return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        it = ctx->graphs.emplace(key, ge).first;
+      }
+      NSE_HIP(ctx, hipGraphLaunch(it->second.exec, ctx->stream));
+      k += kGraphChunk;
+    }
+  }
+  for (; k < end; ++k) {
+    nse_status s = enqueue_step(ctx, h, f, k);
+    if (s != NSE_OK) return s;
+  }
+  return NSE_OK;
+}
+
+nse_status nse_nonlinear_adjoint(nse_ctx* ctx, const double* alpha, const double* n_bar,
+                                 double* alpha_bar) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !n_bar || !alpha_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  return fail(ctx, NSE_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forcing, int64_t step,
+                            double* hist_bar) {
+  if (!ctx) return NSE_ERR_ARG;
+  (void)forcing;
+  if (!hist || !hist_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  if (step < 0) return fail(ctx, NSE_ERR_ARG, "step must be >= 0");
+  return fail(ctx, NSE_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !grid_out) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = (const double2*)alpha;
+  in.coef[0] = 1.0;
+  int64_t goff = 0;
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_synthesis(v, in, SYNTH_GRID, ctx->stream));
+    NSE_HIP(ctx, launch_ring(v, g.plan, SYNTH_GRID, grid_out + goff, ctx->stream));
+    goff += (int64_t)3 * g.nlat * g.M;
+  }
+  return NSE_OK;
+}
+
+nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m, double* out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!out) return fail(ctx, NSE_ERR_ARG, "out is NULL");
+  if (member < 0 || member >= (int)ctx->members.size())
+    return fail(ctx, NSE_ERR_ARG, "member %d out of range", member);
+  const Group& g = ctx->groups[ctx->member_group[member]];
+  if (m < 0 || m > g.N) return fail(ctx, NSE_ERR_ARG, "order m = %d outside 0..%d", m, g.N);
+  const size_t count = (size_t)(g.N + 2 - m) * g.nh;
+  NSE_HIP(ctx, hipMemcpyAsync(out, g.d_T1 + table_offset(g.N, m, g.nh), sizeof(double) * count,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+  return NSE_OK;
+}
+
+nse_status nse_profile_enable(nse_ctx* ctx, int32_t enable) {
+  if (!ctx) return NSE_ERR_ARG;
+  nse_status s = collect_profile(ctx);
+  if (s != NSE_OK) return s;
+  for (int k = 0; k < NSE_KERNEL_KINDS; ++k) {
+    ctx->prof_count[k] = 0;
+    ctx->prof_ms[k] = 0.0;
+  }
+  ctx->profiling = enable != 0;
+  return NSE_OK;
+}
+
+nse_status nse_profile_read(nse_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (kind < 0 || kind >= NSE_KERNEL_KINDS)
+    return fail(ctx, NSE_ERR_ARG, "kernel kind %d out of range", kind);
+  nse_status s = collect_profile(ctx);
+  if (s != NSE_OK) return s;
+  if (launches) *launches = ctx->prof_count[kind];
+  if (total_ms) *total_ms = ctx->prof_ms[kind];
+  ctx->prof_count[kind] = 0;
+  ctx->prof_ms[kind] = 0.0;
+  return NSE_OK;
+}
+
+nse_status nse_sync(nse_ctx* ctx) {
+  if (!ctx) return NSE_ERR_ARG;
+  NSE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->params.flags & NSE_FLAG_CHECK_FINITE) {
+    int flag = 0;
+    NSE_HIP(ctx, hipMemcpy(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+      NSE_HIP(ctx, hipMemset(ctx->d_flag, 0, sizeof(int)));
+      return fail(ctx, NSE_ERR_NONFINITE, "a step produced NaN or Inf");
+    }
+  }
+  return NSE_OK;
+}
+
+}  // extern "C"

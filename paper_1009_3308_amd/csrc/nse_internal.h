@@ -1,0 +1,89 @@
+// Internal declarations shared by the HIP sources of libnse_sphere.so.
+// Nothing here is part of the C ABI (include/nse_sphere.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace nse {
+
+constexpr int kMaxSources = 6;   // predictor terms of NDF_5 (q + 1 <= 6)
+constexpr int kMaxStepCoef = 7;  // c_0 .. c_{q+1} of NDF_5
+constexpr int kMaxRadices = 16;
+constexpr int kMaxM = 2048;      // largest supported longitude count (two LDS rows <= 64 KiB)
+constexpr int kRingThreads = 256;
+
+// Slot of (l, m) inside one member: m-major, l fastest.
+__host__ __device__ inline int64_t coeff_offset(int N, int m) {
+  return (int64_t)m * (2 * N + 3 - m) / 2;
+}
+// Start of order m in a table that stores l = m .. N+1 for nh latitudes.
+__host__ __device__ inline int64_t table_offset(int N, int m, int nh) {
+  return (int64_t)nh * ((int64_t)m * (2 * N + 5 - m) / 2);
+}
+__host__ __device__ inline int64_t table_size(int N, int nh) {
+  return (int64_t)nh * ((int64_t)(N + 1) * (N + 4) / 2);
+}
+
+// Device view of one truncation group (members sharing N and nlat).
+struct GroupView {
+  int N, nlat, nh, M, nb;   // nh = northern latitudes incl. the equator if nlat is odd
+  const double* mu;         // [nh] Gauss-Legendre nodes, descending
+  const double* w;          // [nh]
+  const double* T1;         // [m][l-m][p]  FP64, l = m..N+1
+  const double* T2;         // [m][p][l-m]  FP64, l = m..N+1
+  const float* T1f;         // FP32 copies (precision modes), may be null
+  const float* T2f;
+  double2* F;               // [nb][4][nlat][N+1] Fourier coefficients of grid fields
+  double2* W;               // [nb][N+1][2][nh] weighted even/odd analysis input
+  const double2* tw;        // [M] exp(-2 pi i k / M)
+  const int64_t* off;       // [nb] complex-slot offset of each member in a state
+  const double* nu;         // [nb]
+};
+
+struct FftPlan {
+  int nstages;
+  int radix[kMaxRadices];
+};
+
+// Input of the synthesis: sum_i coef[i] * src[i] (predictor or plain state).
+struct SynthInput {
+  const double2* src[kMaxSources];
+  double coef[kMaxSources];
+  int nsrc;
+  double coriolis;  // 2 Omega sqrt(4 pi / 3): absolute-vorticity fold of zeta[1,0]
+};
+
+enum SynthMode { SYNTH_NONLINEAR = 0, SYNTH_GRID = 1 };
+enum AnalMode { ANAL_NONLINEAR = 0, ANAL_STEP_ITER = 1, ANAL_STEP_FINAL = 2 };
+
+struct AnalOutput {
+  int mode;
+  double2* n_out;            // ANAL_NONLINEAR: state array
+  double2* hist;             // step modes: [depth][state]
+  int64_t state_count;
+  int depth;                 // order + 1
+  int ncoef;                 // c_0 .. c_{ncoef-1}
+  double c[kMaxStepCoef];
+  double h;
+  const double2* forcing;    // may be null
+  double2* iter;             // ANAL_STEP_ITER output
+  int* nonfinite;            // may be null
+};
+
+// Launchers (each enqueues on `s` and returns the launch status).
+hipError_t launch_legendre_table(const GroupView& g, double* T1, double* T2, float* T1f,
+                                 float* T2f, hipStream_t s);
+hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, hipStream_t s);
+hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
+                       hipStream_t s);
+hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s);
+
+// Host numerics.
+void gauss_legendre(int n, std::vector<double>& mu, std::vector<double>& w);
+bool fft_factor(int M, FftPlan& plan);
+
+}  // namespace nse
