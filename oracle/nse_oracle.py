@@ -104,7 +104,7 @@ def gauss_legendre(n: int):
 
     Newton's method on the Legendre polynomial P_n, evaluated by its three-term
     recurrence, from the asymptotic guesses cos(pi (k - 1/4)/(n + 1/2)).
-    Weights w = 2 / ((1 - x^2) P_n'(x)^2).
+    Weights w = 2 / ((1 - x^2) P_n'(x)^2), with 1 - x^2 formed as (1 - x)(1 + x).
     """
     k = torch.arange(1, n + 1, dtype=F64)
     x = torch.cos(math.pi * (k - 0.25) / (n + 0.5))
@@ -113,7 +113,7 @@ def gauss_legendre(n: int):
         p = x.clone()
         for j in range(2, n + 1):
             p_prev, p = p, ((2 * j - 1) * x * p - (j - 1) * p_prev) / j
-        dp = n * (x * p - p_prev) / (x * x - 1.0)
+        dp = n * (p_prev - x * p) / ((1.0 - x) * (1.0 + x))
         dx = p / dp
         x = x - dx
         if float(dx.abs().max()) < 1e-16:
@@ -122,8 +122,8 @@ def gauss_legendre(n: int):
     p = x.clone()
     for j in range(2, n + 1):
         p_prev, p = p, ((2 * j - 1) * x * p - (j - 1) * p_prev) / j
-    dp = n * (x * p - p_prev) / (x * x - 1.0)
-    w = 2.0 / ((1.0 - x * x) * dp * dp)
+    dp = n * (p_prev - x * p) / ((1.0 - x) * (1.0 + x))
+    w = 2.0 / ((1.0 - x) * (1.0 + x) * dp * dp)
     return x, w
 
 
@@ -136,7 +136,8 @@ class Grid:
         self.nlat = nlat
         self.M = 2 * nlat
         self.mu, self.w = gauss_legendre(nlat)
-        self.sin = torch.sqrt(1.0 - self.mu * self.mu)
+        # (1 - mu)(1 + mu) keeps full relative accuracy next to the poles
+        self.sin = torch.sqrt((1.0 - self.mu) * (1.0 + self.mu))
         self.phi = 2.0 * math.pi * torch.arange(self.M, dtype=F64) / self.M
 
     def quad(self, g: torch.Tensor) -> torch.Tensor:
