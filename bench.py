@@ -118,6 +118,9 @@ def main():
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-t511", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB read + 256 MiB write kernel, the "
+                         "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
@@ -137,6 +140,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 268435456 bytes done")
+        del src, dst
 
     N, nu = 255, 1e-5
     log(f"bench: T255 FP64 warmup={args.warmup} steps={args.steps}")
