@@ -50,7 +50,7 @@ def algorithmic_bytes(N, nlat, order, nsrc):
     nh = (nlat + 1) // 2
     slots = (N + 1) * (N + 2) // 2
     F = 4 * nlat * (N + 1) * 16
-    W = (N + 1) * 2 * nh * 16
+    W = nlat * (N + 1) * 16
     return {
         "synthesis": table_bytes(N, nh, 1) + nsrc * slots * 16 + F,
         "ring": F + W,

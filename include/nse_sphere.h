@@ -99,7 +99,7 @@ typedef struct {
  * hipStream_t (NULL = default stream). Returns NSE_ERR_ARG for n_members < 1,
  * N < 1, 2*nlat < 3N+2, nu < 0, order outside 1..5, newton_iters < 1, an
  * unknown precision or flag; NSE_ERR_UNSUPPORTED for a grid whose M has a prime
- * factor other than 2, 3, 5 or M > 2048. *out is NULL on failure. */
+ * factor other than 2, 3, 5 or M > 1536. *out is NULL on failure. */
 nse_status nse_sphere_init(const nse_member* members, int32_t n_members,
                            const nse_params* params, void* hip_stream,
                            nse_ctx** out);

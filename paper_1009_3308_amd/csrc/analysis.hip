@@ -2,9 +2,11 @@
 //
 // Analysis (Section 3, eqs. (disc_ip), (disc_vec_orth_proj); Section 4.2):
 //   n[l,m] = lambda_l^(-1/2) sum_p Pbar[l,m](mu_p) (We_m(p) or Wo_m(p)),
-// where the ring kernel has already applied the longitude DFT, the weights
-// (2 pi / M) w_p and the north/south folding (We for l-m even, Wo for odd),
-// so the sum runs over northern latitudes only. This is
+// where the ring kernel has already applied the longitude DFT and the weights
+// (2 pi / M) w_p, and the rings of each latitude pair are folded here into
+// We = Q(p) + Q(p') (for l-m even) and Wo = Q(p) - Q(p') (odd), using
+// Pbar[l,m](-mu) = (-1)^(l+m) Pbar[l,m](mu), so the sum runs over northern
+// latitudes only. This is
 // (u . Grad(zeta + 2 Omega cos theta), Y[l,m])_M lambda^(-1/2)
 // = (B(u,u) + C u, Z[l,m])_M (eqs. (app1_weak_form), (short_nonlin1), (C)).
 //
@@ -13,52 +15,87 @@
 // then either stored as the next fixed-point iterate or written to hist[0]
 // after rotating hist[j] <- hist[j-1].
 //
-// One thread per degree l (coalesced reads of T2[m][p][l-m] across the
-// wavefront); workgroups over (order m, block of degrees, member).
+// Workgroups of four waves per (order m, tile of 64 degrees, member): one
+// thread per degree l (coalesced reads of T2[m][p][l-m] across the wavefront),
+// each wave summing a quarter of the northern latitudes, partial sums added
+// through LDS. Orders are taken in XCD-local chunks of four neighbouring m so
+// that the strided reads of W[lat][m] share L2 lines.
 #include "nse_internal.h"
 
 namespace nse {
 
-constexpr int kAnalThreads = 64;
+constexpr int kAnalWaves = 4;
+constexpr int kAnalThreads = 64 * kAnalWaves;
+
+size_t analysis_lds_bytes(int nh) {
+  return 2 * sizeof(double2) * (size_t)nh + sizeof(double) * 2 * kAnalThreads;
+}
 
 __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutput out) {
-  const int m = blockIdx.x;
-  const int b = blockIdx.z;
   const int N = g.N, nh = g.nh;
+  const int ntile = (N + 1 + 63) / 64;
+  const int item = xcd_item(blockIdx.x, 4 * ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
+  if (m > N || tile * 64 > N - m) return;  // uniform across the workgroup
+  const int b = blockIdx.y;
   const int L = N + 2 - m;  // row length of T2 for this order
-  extern __shared__ double2 wsh[];  // [2][nh]
-  const double2* Wm = g.W + ((int64_t)b * (N + 1) + m) * 2 * nh;
-  for (int i = threadIdx.x; i < 2 * nh; i += blockDim.x) wsh[i] = Wm[i];
+  extern __shared__ double2 wsh[];  // [2][nh] then [2][kAnalThreads] doubles
+  double* red = reinterpret_cast<double*>(wsh + 2 * nh);
+  // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p')
+  const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
+  for (int p = threadIdx.x; p < nh; p += blockDim.x) {
+    const double2 qn = Wb[(int64_t)p * (N + 1)];
+    const double2 qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+    wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
+    wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
+  }
   __syncthreads();
 
-  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = tile * 64 + lane;
   const int l = m + k;
-  if (l > N) return;
-  const double2* Ws = wsh + ((k & 1) ? nh : 0);
-  const double* t = g.T2 + table_offset(N, m, nh) + k;
+  const int pq = (nh + kAnalWaves - 1) / kAnalWaves;
+  const int p0 = wave * pq;
+  const int p1 = min(nh, p0 + pq);
   double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
-  int p = 0;
+  if (l <= N) {
+    const double2* Ws = wsh + ((k & 1) ? nh : 0);
+    const double* t = g.T2 + table_offset(N, m, nh) + k;
+    int p = p0;
 #pragma unroll 4
-  for (; p + 1 < nh; p += 2) {
-    const double t0 = t[(int64_t)p * L];
-    const double t1 = t[(int64_t)(p + 1) * L];
-    const double2 w0 = Ws[p], w1 = Ws[p + 1];
-    ax = fma(t0, w0.x, ax);
-    ay = fma(t0, w0.y, ay);
-    bx = fma(t1, w1.x, bx);
-    by = fma(t1, w1.y, by);
+    for (; p + 1 < p1; p += 2) {
+      const double t0 = t[(int64_t)p * L];
+      const double t1 = t[(int64_t)(p + 1) * L];
+      const double2 w0 = Ws[p], w1 = Ws[p + 1];
+      ax = fma(t0, w0.x, ax);
+      ay = fma(t0, w0.y, ay);
+      bx = fma(t1, w1.x, bx);
+      by = fma(t1, w1.y, by);
+    }
+    if (p < p1) {
+      const double t0 = t[(int64_t)p * L];
+      const double2 w0 = Ws[p];
+      ax = fma(t0, w0.x, ax);
+      ay = fma(t0, w0.y, ay);
+    }
   }
-  if (p < nh) {
-    const double t0 = t[(int64_t)p * L];
-    const double2 w0 = Ws[p];
-    ax = fma(t0, w0.x, ax);
-    ay = fma(t0, w0.y, ay);
+  red[threadIdx.x] = ax + bx;
+  red[kAnalThreads + threadIdx.x] = ay + by;
+  __syncthreads();
+  if (wave != 0 || l > N) return;
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int w = 0; w < kAnalWaves; ++w) {
+    sx += red[w * 64 + lane];
+    sy += red[kAnalThreads + w * 64 + lane];
   }
   const double lam = (double)l * (l + 1);
   double2 n = make_double2(0.0, 0.0);
   if (l >= 1) {
     const double r = 1.0 / sqrt(lam);
-    n = make_double2((ax + bx) * r, m == 0 ? 0.0 : (ay + by) * r);
+    n = make_double2(sx * r, m == 0 ? 0.0 : sy * r);
   }
   const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
   if (out.mode == ANAL_NONLINEAR) {
@@ -104,9 +141,9 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
 
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s) {
   dim3 block(kAnalThreads);
-  dim3 grid(g.N + 1, (g.N + 1 + kAnalThreads - 1) / kAnalThreads, g.nb);
-  const size_t lds = 2 * sizeof(double2) * (size_t)g.nh;
-  hipLaunchKernelGGL(k_analysis, grid, block, lds, s, g, out);
+  const int ntile = (g.N + 1 + 63) / 64;
+  dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
+  hipLaunchKernelGGL(k_analysis, grid, block, analysis_lds_bytes(g.nh), s, g, out);
   return hipGetLastError();
 }
 

@@ -55,26 +55,32 @@ void gauss_legendre(int n, std::vector<double>& mu, std::vector<double>& w) {
   }
 }
 
-// Splits M into radix-4 stages first, then 5, 3, 2; false if M has another
-// prime factor or too many stages.
+// Splits M into radix-8 stages first, then 4, 2 and the odd radices 5, 3 last,
+// so that the stride Ns = (product of earlier radices) is a power of two for
+// every stage but those after an odd radix; false if M has another prime
+// factor or too many stages.
 bool fft_factor(int M, FftPlan& plan) {
   plan.nstages = 0;
   if (M < 2) return false;
   int r = M;
-  while (r % 4 == 0 && r > 4) {
-    if (plan.nstages >= kMaxRadices) return false;
-    plan.radix[plan.nstages++] = 4;
-    r /= 4;
-  }
-  const int rad[4] = {5, 4, 3, 2};
-  for (int i = 0; i < 4; ++i) {
+  const int rad[5] = {8, 4, 2, 5, 3};
+  for (int i = 0; i < 5; ++i) {
     while (r % rad[i] == 0) {
       if (plan.nstages >= kMaxRadices) return false;
       plan.radix[plan.nstages++] = rad[i];
       r /= rad[i];
     }
   }
-  return r == 1;
+  if (r != 1) return false;
+  int ns = 1;
+  for (int st = 0; st < plan.nstages; ++st) {
+    int lg = -1;
+    for (int b = 0; b < 31; ++b)
+      if ((1 << b) == ns) lg = b;
+    plan.ns_log2[st] = lg;
+    ns *= plan.radix[st];
+  }
+  return true;
 }
 
 }  // namespace nse

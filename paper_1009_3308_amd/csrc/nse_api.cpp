@@ -60,7 +60,7 @@ struct Group {
     GroupView g = view();
     g.nb = 1;
     g.F = d_F + (int64_t)i * 4 * nlat * (N + 1);
-    g.W = d_W + (int64_t)i * (N + 1) * 2 * nh;
+    g.W = d_W + (int64_t)i * nlat * (N + 1);
     g.off = d_off + i;
     g.nu = d_nu + i;
     return g;
@@ -163,7 +163,6 @@ void step_scheme(int p, int64_t k, std::vector<double>& c, std::vector<double>& 
 
 int min_nlat(int N) { return (3 * N + 2 + 1) / 2; }
 
-size_t synth_lds(int N) { return sizeof(double2) * (size_t)((N + 3) + 4 * (N + 2)); }
 
 void free_group(Group& g) {
   (void)hipFree(g.d_mu);
@@ -209,7 +208,7 @@ nse_status build_group(nse_ctx* c, Group& g) {
     NSE_HIP(c, dalloc(&g.d_T2f, ts));
   }
   NSE_HIP(c, dalloc(&g.d_F, (size_t)nb * 4 * g.nlat * (g.N + 1)));
-  NSE_HIP(c, dalloc(&g.d_W, (size_t)nb * (g.N + 1) * 2 * g.nh));
+  NSE_HIP(c, dalloc(&g.d_W, (size_t)nb * g.nlat * (g.N + 1)));
   std::vector<double2> tw(g.M);
   const long double two_pi = 6.283185307179586476925286766559005768L;
   for (int k = 0; k < g.M; ++k) {
@@ -409,7 +408,8 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
                "member %d: M = %d must be <= %d and factor into 2, 3 and 5", i, 2 * m.nlat, kMaxM);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
     }
-    if (synth_lds(m.N) > 65536) {
+    if (synthesis_lds_bytes(m.N) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
+        analysis_lds_bytes((m.nlat + 1) / 2) > 65536) {
       snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,
                m.N);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);

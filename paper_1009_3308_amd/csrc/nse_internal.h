@@ -13,8 +13,20 @@ namespace nse {
 constexpr int kMaxSources = 6;   // predictor terms of NDF_5 (q + 1 <= 6)
 constexpr int kMaxStepCoef = 7;  // c_0 .. c_{q+1} of NDF_5
 constexpr int kMaxRadices = 16;
-constexpr int kMaxM = 2048;      // largest supported longitude count (two LDS rows <= 64 KiB)
-constexpr int kRingThreads = 256;
+constexpr int kMaxM = 1536;      // largest supported longitude count (ring LDS <= 64 KiB)
+
+// Linear work item of block `bid` such that the blocks the dispatcher places on one
+// XCD (bid % 8, round-robin) take consecutive chunks of `chunk` items, and chunks
+// alternate between XCDs. Neighbouring items then share that XCD's L2.
+__host__ __device__ inline int xcd_item(int bid, int chunk) {
+  const int x = bid & 7, k = bid >> 3;
+  return ((x + 8 * (k / chunk)) * chunk) + (k % chunk);
+}
+// Grid size covering `items` work items for xcd_item (a multiple of 8 * chunk).
+__host__ __device__ inline int xcd_grid(int items, int chunk) {
+  const int per = 8 * chunk;
+  return ((items + per - 1) / per) * per;
+}
 
 // Slot of (l, m) inside one member: m-major, l fastest.
 __host__ __device__ inline int64_t coeff_offset(int N, int m) {
@@ -37,8 +49,8 @@ struct GroupView {
   const double* T2;         // [m][p][l-m]  FP64, l = m..N+1
   const float* T1f;         // FP32 copies (precision modes), may be null
   const float* T2f;
-  double2* F;               // [nb][4][nlat][N+1] Fourier coefficients of grid fields
-  double2* W;               // [nb][N+1][2][nh] weighted even/odd analysis input
+  double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
+  double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
   const double2* tw;        // [M] exp(-2 pi i k / M)
   const int64_t* off;       // [nb] complex-slot offset of each member in a state
   const double* nu;         // [nb]
@@ -47,6 +59,7 @@ struct GroupView {
 struct FftPlan {
   int nstages;
   int radix[kMaxRadices];
+  int ns_log2[kMaxRadices];  // log2 of the stride Ns before each stage, -1 if not a power of 2
 };
 
 // Input of the synthesis: sum_i coef[i] * src[i] (predictor or plain state).
@@ -81,6 +94,11 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s);
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s);
+
+// Dynamic LDS of the launches (validated against 64 KiB at init).
+size_t synthesis_lds_bytes(int N);
+size_t ring_lds_bytes(int M);
+size_t analysis_lds_bytes(int nh);
 
 // Host numerics.
 void gauss_legendre(int n, std::vector<double>& mu, std::vector<double>& w);

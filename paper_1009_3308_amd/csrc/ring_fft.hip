@@ -1,22 +1,25 @@
 // Longitude transforms and the grid product (Section 4.2: FFT in the
 // azimuthal direction at the M equispaced longitudes of eq. (quadrule)).
 //
-// One workgroup per northern/southern ring pair (p, nlat-1-p). The two rings
-// share every complex FFT: for a field with Fourier coefficients G^N_m (north)
-// and G^S_m (south), m = 0..N, the length-M sequence
-//   x_m = G^N_m + i G^S_m,  x_{M-m} = conj(G^N_m) + i conj(G^S_m)
-// has the inverse DFT g^N_j + i g^S_j (both rings' real grid values). The
-// product q = (f0 f2 - f1 f3) / sin^2(theta) = u . Grad(zeta + 2 Omega cos theta)
-// is formed in registers, then one forward FFT of q^N + i q^S gives both rings'
-// spectra. The quadrature factor (2 pi / M) w_p of eq. (quadrule) is applied
-// and the analysis input is written as even/odd combinations
-//   We_m = c (Q^N_m + Q^S_m),  Wo_m = c (Q^N_m - Q^S_m),
-// so that the Legendre analysis runs over northern latitudes only.
+// One workgroup per latitude ring. Two real fields share one complex FFT: for
+// fields a, b with Fourier coefficients G^a_m, G^b_m, m = 0..N, the length-M
+// sequence
+//   x_m = G^a_m + i G^b_m,  x_{M-m} = conj(G^a_m) + i conj(G^b_m)
+// has the inverse DFT g^a_j + i g^b_j. Pairing (f0, f2) and (f1, f3) makes each
+// product of the advection term the real part times the imaginary part of one
+// transform:
+//   q = (f0 f2 - f1 f3) / sin^2(theta) = u . Grad(zeta + 2 Omega cos theta).
+// One forward FFT of q gives its spectrum Q_m; the quadrature factor
+// (2 pi / M) w_p of eq. (quadrule) is applied and Q_m, m = 0..N, is written for
+// the ring (W[lat][m]); the analysis folds the two rings of each latitude
+// pair.
 //
-// The FFT is a mixed-radix (4, 5, 3, 2) Stockham transform in LDS: each stage
-// reads R values at stride M/R, applies twiddles from a global table
-// exp(-2 pi i k / M), performs a radix-R butterfly and writes in autosort
-// order to the other LDS buffer.
+// The FFT is a mixed-radix (8, 4, 2, 5, 3) Stockham transform done in place in
+// LDS: each stage reads R values at stride M/R into registers, applies
+// twiddles from a half table exp(-2 pi i e / M), e < M/2, kept in LDS, performs
+// a radix-R butterfly and writes back in autosort order after a barrier. The
+// two inverse transforms run in the same stages. With the odd radices last,
+// the stage strides are powers of two and the index arithmetic is shifts.
 #include "nse_internal.h"
 
 namespace nse {
@@ -28,7 +31,6 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 // s * i * a for s = +-1
 __device__ __forceinline__ double2 cmul_si(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
 
@@ -40,6 +42,7 @@ constexpr double kC2 = -0.80901699437494742410;
 constexpr double kS1 = 0.95105651629515357212;
 constexpr double kS2 = 0.58778525229247312917;
 
+// DFT of length R with kernel exp(s 2 pi i j k / R), in place.
 template <int R>
 __device__ __forceinline__ void butterfly(double2* v, double s) {
   if constexpr (R == 2) {
@@ -73,179 +76,233 @@ __device__ __forceinline__ void butterfly(double2* v, double s) {
     v[4] = csub(c1, s1);
     v[2] = cadd(c2, s2);
     v[3] = csub(c2, s2);
+  } else if constexpr (R == 8) {
+    // radix 8 from two radix-4 transforms of the even and odd samples
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    butterfly<4>(e, s);
+    butterfly<4>(o, s);
+    constexpr double h = 0.70710678118654752440;  // 1 / sqrt(2)
+    const double2 o1 = make_double2(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+    const double2 o2 = cmul_si(o[2], s);
+    const double2 o3 = make_double2(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
   }
 }
 
-// One Stockham stage of radix R from `in` to `out` (both LDS, length M).
+// LDS rows are padded by one slot every 16 complex values so that the strided
+// accesses of the Stockham stages spread over the LDS banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+__host__ __device__ inline int padded_len(int M) { return M + (M >> 4) + 1; }
+
+// exp(-2 pi i e / M) from the half table tw[0 .. M/2) in LDS.
+__device__ __forceinline__ double2 twiddle(const double2* tw, int e, int half) {
+  if (e < half) return tw[e];
+  const double2 t = tw[e - half];
+  return make_double2(-t.x, -t.y);
+}
+
+// q = j / Ns, k = j mod Ns (shifts when Ns is a power of two).
+__device__ __forceinline__ void split(int j, int Ns, int lg, int& q, int& k) {
+  if (lg >= 0) {
+    q = j >> lg;
+    k = j & (Ns - 1);
+  } else {
+    q = j / Ns;
+    k = j - q * Ns;
+  }
+}
+
+// In-place Stockham stage of radix R on NA arrays in LDS (NA = 1 or 2): every
+// thread first reads, twiddles and transforms all butterflies it owns into
+// registers, then (after a barrier) writes them in autosort order.
 // sign = -1 forward (exp(-2 pi i jk/M)), +1 inverse.
-template <int R>
-__device__ void stage(const double2* __restrict__ in, double2* __restrict__ out, int M, int Ns,
-                      const double2* __restrict__ tw, double sign) {
+template <int R, int NA, int MAXM, int NT>
+__device__ __forceinline__ void stage(double2* x0, double2* x1, int M, int Ns, int lg,
+                                      const double2* tw, double sign) {
+  constexpr int MAXB = ((MAXM / R) * NA + NT - 1) / NT;
   const int span = M / R;
   const int step = M / (Ns * R);
-  for (int j = threadIdx.x; j < span; j += blockDim.x) {
-    double2 v[R];
+  const int total = span * NA;
+  const int half = M >> 1;
+  double2 v[MAXB][R];
+  int dst[MAXB];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[j + r * span];
-    const int k = j % Ns;
-    if (k != 0) {
+  for (int c = 0; c < MAXB; ++c) {
+    const int t = threadIdx.x + c * NT;
+    dst[c] = -1;
+    if (t < total) {
+      const int a = (NA == 1) ? 0 : (t >= span ? 1 : 0);
+      const int j = t - a * span;
+      const double2* x = a ? x1 : x0;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        double2 w = tw[(r * k * step) % M];
-        w.y *= -sign;  // table holds exp(-2 pi i e / M); forward uses it as is
-        v[r] = cmul(v[r], w);
+      for (int r = 0; r < R; ++r) v[c][r] = x[pad(j + r * span)];
+      int q, k;
+      split(j, Ns, lg, q, k);
+      if (k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = twiddle(tw, r * k * step, half);
+          w.y *= -sign;  // the table holds exp(-2 pi i e / M); forward uses it as is
+          v[c][r] = cmul(v[c][r], w);
+        }
       }
+      butterfly<R>(v[c], sign);
+      dst[c] = (a << 24) | (q * Ns * R + k);
     }
-    butterfly<R>(v, sign);
-    const int idx = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[idx + r * Ns] = v[r];
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (dst[c] >= 0) {
+      double2* x = (dst[c] >> 24) ? x1 : x0;
+      const int idx = dst[c] & 0xffffff;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[pad(idx + r * Ns)] = v[c][r];
+    }
+  }
+  __syncthreads();
 }
 
-// Full transform; returns the buffer that holds the result.
-__device__ double2* fft(double2* a, double2* b, const FftPlan& plan, int M,
-                        const double2* __restrict__ tw, double sign) {
+// Full in-place transform of one or two LDS arrays.
+template <int NA, int MAXM, int NT>
+__device__ void fft(double2* x0, double2* x1, const FftPlan& plan, int M, const double2* tw,
+                    double sign) {
   int Ns = 1;
   for (int st = 0; st < plan.nstages; ++st) {
     const int R = plan.radix[st];
+    const int lg = plan.ns_log2[st];
     switch (R) {
-      case 2: stage<2>(a, b, M, Ns, tw, sign); break;
-      case 3: stage<3>(a, b, M, Ns, tw, sign); break;
-      case 4: stage<4>(a, b, M, Ns, tw, sign); break;
-      default: stage<5>(a, b, M, Ns, tw, sign); break;
+      case 2: stage<2, NA, MAXM, NT>(x0, x1, M, Ns, lg, tw, sign); break;
+      case 3: stage<3, NA, MAXM, NT>(x0, x1, M, Ns, lg, tw, sign); break;
+      case 4: stage<4, NA, MAXM, NT>(x0, x1, M, Ns, lg, tw, sign); break;
+      case 5: stage<5, NA, MAXM, NT>(x0, x1, M, Ns, lg, tw, sign); break;
+      default: stage<8, NA, MAXM, NT>(x0, x1, M, Ns, lg, tw, sign); break;
     }
-    __syncthreads();
-    double2* t = a;
-    a = b;
-    b = t;
     Ns *= R;
   }
-  return a;
 }
 
-// Loads the pair spectrum of field f into x (length M) for rings p (north) and ps.
-__device__ void load_pair(double2* x, const double2* __restrict__ Fn, const double2* __restrict__ Fs,
-                          int N, int M) {
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    double2 v = make_double2(0.0, 0.0);
-    if (j == 0) {
-      v = make_double2(Fn[0].x, Fs[0].x);
-    } else if (j <= N) {
-      const double2 gn = Fn[j], gs = Fs[j];
-      v = make_double2(gn.x - gs.y, gn.y + gs.x);        // gn + i gs
-    } else if (j >= M - N) {
-      const double2 gn = Fn[M - j], gs = Fs[M - j];
-      v = make_double2(gn.x + gs.y, -gn.y + gs.x);       // conj(gn) + i conj(gs)
+// Spectrum of the field pair (a, b) of one ring into x[0..M):
+// x_m = G^a_m + i G^b_m, x_{M-m} = conj(G^a_m) + i conj(G^b_m), zero elsewhere.
+// G[m] is read from F[f][m][lat] (stride nlat between orders).
+__device__ void load_pair(double2* x, const double2* __restrict__ Fa,
+                          const double2* __restrict__ Fb, int lat, int N, int M, int nlat) {
+  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
+    const double2 ga = Fa[(int64_t)m * nlat + lat];
+    const double2 gb = Fb[(int64_t)m * nlat + lat];
+    if (m == 0) {
+      x[0] = make_double2(ga.x, gb.x);
+    } else {
+      x[pad(m)] = make_double2(ga.x - gb.y, ga.y + gb.x);        // ga + i gb
+      x[pad(M - m)] = make_double2(ga.x + gb.y, -ga.y + gb.x);   // conj(ga) + i conj(gb)
     }
-    x[j] = v;
   }
+  for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
 }
 
 }  // namespace
 
-template <int PTS>
-__global__ __launch_bounds__(kRingThreads) void k_ring(GroupView g, FftPlan plan, int mode,
-                                                       double* grid_out) {
-  const int p = blockIdx.x;
-  const int b = blockIdx.z;
+size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(M) + M / 2); }
+
+// One workgroup per ring; rings are taken in XCD-local chunks of eight
+// neighbouring latitudes so that the strided reads of F share L2 lines.
+// MAXM: the largest M of the size class this instance serves and NT its
+// workgroup size (register arrays are sized from both).
+template <int MAXM, int NT>
+__global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode,
+                                             double* grid_out) {
+  constexpr int PTS = (MAXM + NT - 1) / NT;
   const int N = g.N, M = g.M, nlat = g.nlat;
-  const int ps = nlat - 1 - p;
+  const int lat = xcd_item(blockIdx.x, 8);
+  if (lat >= nlat) return;
+  const int b = blockIdx.y;
+  const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
+  const int PL = padded_len(M);
   extern __shared__ double2 lds[];
-  double2* bufA = lds;
-  double2* bufB = lds + M;
+  double2* A0 = lds;
+  double2* A1 = lds + PL;
+  double2* tw = lds + 2 * PL;
+  for (int j = threadIdx.x; j < M / 2; j += blockDim.x) tw[j] = g.tw[j];
   const double x = g.mu[p];
   const double sin2 = (1.0 - x) * (1.0 + x);
-  const double2* Fb = g.F + (int64_t)b * 4 * nlat * (N + 1);
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* F0 = g.F + (int64_t)b * 4 * fstride;
 
   if (mode == SYNTH_GRID) {
-    // u_theta = f0 / sin, u_phi = -f1 / sin, zeta = f2 for both rings.
+    // u_theta = f0 / sin, u_phi = -f1 / sin, zeta = f2
     const double rs = 1.0 / sqrt(sin2);
-    for (int f = 0; f < 3; ++f) {
-      const double2* Ff = Fb + (int64_t)f * nlat * (N + 1);
-      load_pair(bufA, Ff + (int64_t)p * (N + 1), Ff + (int64_t)ps * (N + 1), N, M);
-      __syncthreads();
-      const double2* res = fft(bufA, bufB, plan, M, g.tw, 1.0);
-      const double sc = (f == 0) ? rs : (f == 1 ? -rs : 1.0);
-      double* gn = grid_out + (((int64_t)b * 3 + f) * nlat + p) * M;
-      double* gs = grid_out + (((int64_t)b * 3 + f) * nlat + ps) * M;
-      for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        const double2 v = res[j];
-        gn[j] = sc * v.x;
-        if (ps != p) gs[j] = sc * v.y;
-      }
-      __syncthreads();
+    load_pair(A0, F0, F0 + fstride, lat, N, M, nlat);
+    load_pair(A1, F0 + 2 * fstride, F0 + 2 * fstride, lat, N, M, nlat);
+    __syncthreads();
+    fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+    double* g0 = grid_out + ((int64_t)0 * nlat + lat) * M;
+    double* g1 = grid_out + ((int64_t)1 * nlat + lat) * M;
+    double* g2 = grid_out + ((int64_t)2 * nlat + lat) * M;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+      const double2 v0 = A0[pad(j)], v1 = A1[pad(j)];
+      g0[j] = rs * v0.x;
+      g1[j] = -rs * v0.y;
+      g2[j] = v1.x;
     }
     return;
   }
 
-  double qn[PTS], qs[PTS], hn[PTS], hs[PTS];
+  // inverse transforms of f0 + i f2 and f1 + i f3
+  load_pair(A0, F0, F0 + 2 * fstride, lat, N, M, nlat);
+  load_pair(A1, F0 + fstride, F0 + 3 * fstride, lat, N, M, nlat);
+  __syncthreads();
+  fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
   const double inv_sin2 = 1.0 / sin2;
-  // field order f0, f2 (-> q = f0 f2), f1, f3 (-> q = (q - f1 f3) / sin^2)
-  for (int oi = 0; oi < 4; ++oi) {
-    const int f = (oi == 1) ? 2 : (oi == 2 ? 1 : oi);
-    const double2* Ff = Fb + (int64_t)f * nlat * (N + 1);
-    load_pair(bufA, Ff + (int64_t)p * (N + 1), Ff + (int64_t)ps * (N + 1), N, M);
-    __syncthreads();
-    const double2* res = fft(bufA, bufB, plan, M, g.tw, 1.0);
+  double q[PTS];
 #pragma unroll
-    for (int i = 0; i < PTS; ++i) {
-      const int j = threadIdx.x + i * kRingThreads;
-      double vn = 0.0, vs = 0.0;
-      if (j < M) {
-        const double2 v = res[j];
-        vn = v.x;
-        vs = v.y;
-      }
-      if (oi == 0 || oi == 2) {
-        hn[i] = vn;
-        hs[i] = vs;
-      } else if (oi == 1) {
-        qn[i] = hn[i] * vn;
-        qs[i] = hs[i] * vs;
-      } else {
-        qn[i] = (qn[i] - hn[i] * vn) * inv_sin2;
-        qs[i] = (qs[i] - hs[i] * vs) * inv_sin2;
-      }
+  for (int c = 0; c < PTS; ++c) {
+    const int j = threadIdx.x + c * NT;
+    q[c] = 0.0;
+    if (j < M) {
+      const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
+      q[c] = (z02.x * z02.y - z13.x * z13.y) * inv_sin2;
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < PTS; ++i) {
-    const int j = threadIdx.x + i * kRingThreads;
-    if (j < M) bufA[j] = make_double2(qn[i], qs[i]);
   }
   __syncthreads();
-  const double2* X = fft(bufA, bufB, plan, M, g.tw, -1.0);
-  const double c = (6.283185307179586477 / M) * g.w[p] * (ps == p ? 0.5 : 1.0);
-  double2* Wb = g.W + (int64_t)b * (N + 1) * 2 * g.nh;
+#pragma unroll
+  for (int c = 0; c < PTS; ++c) {
+    const int j = threadIdx.x + c * NT;
+    if (j < M) A0[pad(j)] = make_double2(q[c], 0.0);
+  }
+  __syncthreads();
+  fft<1, MAXM, NT>(A0, A1, plan, M, tw, -1.0);
+  // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
+  // own mirror and is folded twice by the analysis
+  const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
+  double2* Wl = g.W + ((int64_t)b * nlat + lat) * (N + 1);
   for (int m = threadIdx.x; m <= N; m += blockDim.x) {
-    const double2 xm = X[m];
-    const double2 xc = X[(M - m) % M];
-    // Q^N = (X_m + conj X_{M-m}) / 2,  Q^S = (X_m - conj X_{M-m}) / (2 i)
-    const double2 qN = make_double2(0.5 * (xm.x + xc.x), 0.5 * (xm.y - xc.y));
-    const double2 qS = make_double2(0.5 * (xm.y + xc.y), -0.5 * (xm.x - xc.x));
-    Wb[((int64_t)m * 2 + 0) * g.nh + p] = make_double2(c * (qN.x + qS.x), c * (qN.y + qS.y));
-    Wb[((int64_t)m * 2 + 1) * g.nh + p] = make_double2(c * (qN.x - qS.x), c * (qN.y - qS.y));
+    const double2 X = A0[pad(m)];
+    Wl[m] = make_double2(c * X.x, c * X.y);
   }
 }
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s) {
-  dim3 block(kRingThreads);
-  dim3 grid(g.nh, 1, g.nb);
-  const size_t lds = 2 * sizeof(double2) * (size_t)g.M;
-  const int pts = (g.M + kRingThreads - 1) / kRingThreads;
-  if (pts <= 1)
-    hipLaunchKernelGGL(k_ring<1>, grid, block, lds, s, g, plan, mode, grid_out);
-  else if (pts <= 2)
-    hipLaunchKernelGGL(k_ring<2>, grid, block, lds, s, g, plan, mode, grid_out);
-  else if (pts <= 4)
-    hipLaunchKernelGGL(k_ring<4>, grid, block, lds, s, g, plan, mode, grid_out);
-  else if (pts <= 8)
-    hipLaunchKernelGGL(k_ring<8>, grid, block, lds, s, g, plan, mode, grid_out);
+  dim3 grid(xcd_grid(g.nlat, 8), g.nb);
+  const size_t lds = ring_lds_bytes(g.M);
+  if (g.M <= 256)
+    hipLaunchKernelGGL((k_ring<256, 128>), grid, dim3(128), lds, s, g, plan, mode, grid_out);
+  else if (g.M <= 512)
+    hipLaunchKernelGGL((k_ring<512, 256>), grid, dim3(256), lds, s, g, plan, mode, grid_out);
+  else if (g.M <= 768)
+    hipLaunchKernelGGL((k_ring<768, 256>), grid, dim3(256), lds, s, g, plan, mode, grid_out);
+  else if (g.M <= 1024)
+    hipLaunchKernelGGL((k_ring<1024, 512>), grid, dim3(512), lds, s, g, plan, mode, grid_out);
   else
-    hipLaunchKernelGGL(k_ring<16>, grid, block, lds, s, g, plan, mode, grid_out);
+    hipLaunchKernelGGL((k_ring<kMaxM, 512>), grid, dim3(512), lds, s, g, plan, mode, grid_out);
   return hipGetLastError();
 }
 

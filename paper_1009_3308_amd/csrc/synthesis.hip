@@ -16,26 +16,43 @@
 // For the grid-output mode the fields are f0 = d psi/d phi, f1 = sin(theta)
 // d psi/d theta and f2 = zeta (no rotation term), f3 = 0.
 //
-// One workgroup per (order m, block of northern latitudes, member). The
-// panel of coefficients for this m is built in LDS, then each thread streams
-// its latitude column of T1[m][l-m][p] (coalesced across the wavefront) and
-// accumulates even (l-m even) and odd parts separately, giving both the
-// northern value E + O and the mirrored southern value E - O.
+// One workgroup of four waves per (order m, tile of 64 northern latitudes,
+// member). The panel of coefficients for this m is built in LDS; each wave
+// then streams a quarter of the degree range of its latitude column of
+// T1[m][l-m][p] (coalesced across the wavefront), accumulating even (l-m even)
+// and odd parts separately, and the four partial sums are added through LDS.
+// Each latitude yields the northern value E + O and the mirrored southern value
+// E - O. Output F[b][f][m][lat] is written latitude-contiguous.
 #include "nse_internal.h"
 
 namespace nse {
 
-constexpr int kSynthThreads = 128;
+constexpr int kSynthWaves = 4;
+constexpr int kSynthThreads = 64 * kSynthWaves;
+constexpr int kRed = 16;  // partial sums per lane: 4 fields x (E, O) x (re, im)
+
+__host__ __device__ inline int synth_pan_slots(int N) {
+  // panel [L][4] double2, reused afterwards for the cross-wave reduction
+  const int pan = 4 * (N + 2);
+  const int red = kSynthWaves * kRed * 64 / 2;
+  return pan > red ? pan : red;
+}
+
+size_t synthesis_lds_bytes(int N) {
+  return sizeof(double2) * (size_t)((N + 3) + synth_pan_slots(N));
+}
 
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthInput in,
                                                               int mode) {
-  const int m = blockIdx.x;
-  const int b = blockIdx.z;
   const int N = g.N, nh = g.nh, nlat = g.nlat;
+  const int ntile = (nh + 63) / 64;
+  const int m = blockIdx.x / ntile;
+  const int tile = blockIdx.x - m * ntile;
+  const int b = blockIdx.y;
   const int L = N + 2 - m;  // degrees m .. N+1
   extern __shared__ double2 sh[];
-  double2* a = sh;          // [L + 1] state coefficients alpha[l], l = m..N (0 beyond)
-  double2* pan = sh + (L + 1);  // [L][4]
+  double2* a = sh;              // [L + 1] state coefficients alpha[l], l = m..N (0 beyond)
+  double2* pan = sh + (N + 3);  // [L][4]
 
   const int64_t base = g.off[b] + coeff_offset(N, m);
   for (int k = threadIdx.x; k < L + 1; k += blockDim.x) {
@@ -60,7 +77,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     const int l = m + k;
     const double dl = (double)l;
-    // psi and zeta_a at degrees l-1, l, l+1 (zero outside m..N)
+    // psi and zeta_a at degrees l-1, l, l+1 (zero outside 1..N)
     auto psi_at = [&](int kk) -> double2 {
       const int ll = m + kk;
       if (kk < 0 || ll < 1 || ll > N) return make_double2(0.0, 0.0);
@@ -97,56 +114,71 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   }
   __syncthreads();
 
-  const int p = blockIdx.y * blockDim.x + threadIdx.x;
-  if (p >= nh) return;
-  const double* t = g.T1 + table_offset(N, m, nh) + p;
-  double2 e[4], o[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int p = tile * 64 + lane;
+  // even-length quarter of the degree range for this wave
+  const int chunk = ((L + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
+  const int k0 = wave * chunk;
+  const int k1 = min(L, k0 + chunk);
+  double acc[kRed];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    e[f] = make_double2(0.0, 0.0);
-    o[f] = make_double2(0.0, 0.0);
-  }
-  int k = 0;
-#pragma unroll 2
-  for (; k + 1 < L; k += 2) {
-    const double t0 = t[(int64_t)k * nh];
-    const double t1 = t[(int64_t)(k + 1) * nh];
+  for (int i = 0; i < kRed; ++i) acc[i] = 0.0;
+  if (p < nh && k0 < k1) {
+    const double* t = g.T1 + table_offset(N, m, nh) + p;
+    int k = k0;
+#pragma unroll 4
+    for (; k + 1 < k1; k += 2) {
+      const double t0 = t[(int64_t)k * nh];
+      const double t1 = t[(int64_t)(k + 1) * nh];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const double2 A = pan[4 * k + f];
-      const double2 B = pan[4 * (k + 1) + f];
-      e[f].x = fma(t0, A.x, e[f].x);
-      e[f].y = fma(t0, A.y, e[f].y);
-      o[f].x = fma(t1, B.x, o[f].x);
-      o[f].y = fma(t1, B.y, o[f].y);
+      for (int f = 0; f < 4; ++f) {
+        const double2 A = pan[4 * k + f];
+        const double2 B = pan[4 * (k + 1) + f];
+        acc[4 * f + 0] = fma(t0, A.x, acc[4 * f + 0]);
+        acc[4 * f + 1] = fma(t0, A.y, acc[4 * f + 1]);
+        acc[4 * f + 2] = fma(t1, B.x, acc[4 * f + 2]);
+        acc[4 * f + 3] = fma(t1, B.y, acc[4 * f + 3]);
+      }
+    }
+    if (k < k1) {
+      const double t0 = t[(int64_t)k * nh];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double2 A = pan[4 * k + f];
+        acc[4 * f + 0] = fma(t0, A.x, acc[4 * f + 0]);
+        acc[4 * f + 1] = fma(t0, A.y, acc[4 * f + 1]);
+      }
     }
   }
-  if (k < L) {
-    const double t0 = t[(int64_t)k * nh];
+  __syncthreads();  // panel no longer needed: reuse it for the reduction
+  double* red = reinterpret_cast<double*>(pan);  // [wave][kRed][64]
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const double2 A = pan[4 * k + f];
-      e[f].x = fma(t0, A.x, e[f].x);
-      e[f].y = fma(t0, A.y, e[f].y);
-    }
-  }
-  const int ps = nlat - 1 - p;
+  for (int i = 0; i < kRed; ++i) red[(wave * kRed + i) * 64 + lane] = acc[i];
+  __syncthreads();
+  // wave f finishes field f for its 64 latitudes
+  const int f = wave;
   const int nf = (mode == SYNTH_NONLINEAR) ? 4 : 3;
+  if (f >= nf || p >= nh) return;
+  double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    if (f >= nf) break;
-    double2* out = g.F + ((int64_t)(b * 4 + f) * nlat) * (N + 1) + m;
-    out[(int64_t)p * (N + 1)] = make_double2(e[f].x + o[f].x, e[f].y + o[f].y);
-    if (ps != p)
-      out[(int64_t)ps * (N + 1)] = make_double2(e[f].x - o[f].x, e[f].y - o[f].y);
+  for (int w = 0; w < kSynthWaves; ++w) {
+    er += red[(w * kRed + 4 * f + 0) * 64 + lane];
+    ei += red[(w * kRed + 4 * f + 1) * 64 + lane];
+    orr += red[(w * kRed + 4 * f + 2) * 64 + lane];
+    oi += red[(w * kRed + 4 * f + 3) * 64 + lane];
   }
+  double2* out = g.F + ((int64_t)(b * 4 + f) * (N + 1) + m) * nlat;
+  out[p] = make_double2(er + orr, ei + oi);
+  const int ps = nlat - 1 - p;
+  if (ps != p) out[ps] = make_double2(er - orr, ei - oi);
 }
 
 hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, hipStream_t s) {
   dim3 block(kSynthThreads);
-  dim3 grid(g.N + 1, (g.nh + kSynthThreads - 1) / kSynthThreads, g.nb);
-  const size_t lds = sizeof(double2) * (size_t)((g.N + 3) + 4 * (g.N + 2));
-  hipLaunchKernelGGL(k_synthesis, grid, block, lds, s, g, in, mode);
+  const int ntile = (g.nh + 63) / 64;
+  dim3 grid((g.N + 1) * ntile, g.nb);
+  hipLaunchKernelGGL(k_synthesis, grid, block, synthesis_lds_bytes(g.N), s, g, in, mode);
   return hipGetLastError();
 }
 
