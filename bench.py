@@ -82,12 +82,12 @@ def run_steps(sph, hist, f, step0, n):
     sph.step(hist, f, step0, n)
 
 
-def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True):
+def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True, precision="fp64"):
     import nse_inputs as I
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         sph = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, order=2, graph=graph,
-                         stream=stream)
+                         stream=stream, precision=precision)
         hist = sph.new_history()
         hist[0] = pkg.to_device(I.initial_state(N))
         f = pkg.to_device(I.forcing(N))
@@ -106,6 +106,35 @@ def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True):
         ev_ms = ev0.elapsed_time(ev1)
         finite = bool(torch.isfinite(torch.view_as_real(hist[0])).all())
     return sph, hist, f, stream, wall, ev_ms, finite
+
+
+def precision_errors(pkg, torch, N, nu, steps):
+    """Relative l2 error of the grid fields (u_theta, u_phi, zeta) of the reduced-
+    precision runs against the FP64 run after 1 and after `steps` steps."""
+    import numpy as np
+
+    import nse_inputs as I
+    a0, f = pkg.to_device(I.initial_state(N)), pkg.to_device(I.forcing(N))
+    states = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        s = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, precision=prec)
+        h = s.new_history()
+        h[0] = a0
+        s.step(h, f, 0, 1)
+        one = h[0].clone()
+        s.step(h, f, 1, steps - 1)
+        states[prec] = (one, h[0].clone())
+        s.close()
+    s64 = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3)
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        for idx, tag in ((0, "1step"), (1, f"{steps}steps")):
+            g64 = s64.synthesize(states["fp64"][idx])[0].cpu().numpy()
+            glp = s64.synthesize(states[prec][idx])[0].cpu().numpy()
+            out[f"{prec}_field_err_{tag}"] = max(
+                float(np.linalg.norm(glp[i] - g64[i]) / np.linalg.norm(g64[i])) for i in range(3))
+    s64.close()
+    return out
 
 
 def main():
@@ -195,10 +224,18 @@ def main():
              "timed_region_event_ms": round(ev_ms, 3)}
     if not args.no_t511:
         steps511 = max(20, args.steps // 5)
-        log(f"bench: T511 FP64 steps={steps511}")
-        s5, h5, f5, st5, wall5, _, fin5 = time_gpu(pkg, torch, 511, 1e-5, steps511, 10)
-        extra["t511_fp64_steps_per_s"] = round(steps511 / wall5, 2) if fin5 else None
-        s5.close()
+        for prec in ("fp64", "fp32", "bf16x3"):
+            log(f"bench: T511 {prec} steps={steps511}")
+            s5, h5, f5, st5, wall5, _, fin5 = time_gpu(pkg, torch, 511, 1e-5, steps511, 10,
+                                                       precision=prec)
+            extra[f"t511_{prec}_steps_per_s"] = round(steps511 / wall5, 2) if fin5 else None
+            s5.close()
+        for prec in ("fp32", "bf16x3"):
+            if extra.get(f"t511_{prec}_steps_per_s") and extra.get("t511_fp64_steps_per_s"):
+                extra[f"t511_{prec}_speedup_vs_fp64"] = round(
+                    extra[f"t511_{prec}_steps_per_s"] / extra["t511_fp64_steps_per_s"], 3)
+        log("bench: T511 precision errors (200 steps)")
+        extra.update({f"t511_{k}": v for k, v in precision_errors(pkg, torch, 511, 1e-5, 200).items()})
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -24,6 +24,7 @@ SOURCES = [
     "synthesis.hip",
     "ring_fft.hip",
     "analysis.hip",
+    "contract_lp.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

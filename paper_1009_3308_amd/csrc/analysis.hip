@@ -20,17 +20,21 @@
 // each wave summing a quarter of the northern latitudes, partial sums added
 // through LDS. Orders are taken in XCD-local chunks of four neighbouring m so
 // that the strided reads of W[lat][m] share L2 lines.
-#include "nse_internal.h"
+#include "spectral_ops.h"
 
 namespace nse {
 
 constexpr int kAnalWaves = 4;
 constexpr int kAnalThreads = 64 * kAnalWaves;
+constexpr int kBatch = 8;  // table rows per load batch
 
 size_t analysis_lds_bytes(int nh) {
   return 2 * sizeof(double2) * (size_t)nh + sizeof(double) * 2 * kAnalThreads;
 }
 
+// TT: element type of the table and of the products and accumulation (double
+// for NSE_PREC_FP64, float for NSE_PREC_FP32); the cross-wave sums are FP64.
+template <typename TT>
 __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutput out) {
   const int N = g.N, nh = g.nh;
   const int ntile = (N + 1 + 63) / 64;
@@ -39,7 +43,6 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
   const int tile = item - m * ntile;
   if (m > N || tile * 64 > N - m) return;  // uniform across the workgroup
   const int b = blockIdx.y;
-  const int L = N + 2 - m;  // row length of T2 for this order
   extern __shared__ double2 wsh[];  // [2][nh] then [2][kAnalThreads] doubles
   double* red = reinterpret_cast<double*>(wsh + 2 * nh);
   // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p')
@@ -59,30 +62,43 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
   const int pq = (nh + kAnalWaves - 1) / kAnalWaves;
   const int p0 = wave * pq;
   const int p1 = min(nh, p0 + pq);
-  double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+  TT ax = TT(0), ay = TT(0), bx = TT(0), by = TT(0);
   if (l <= N) {
     const double2* Ws = wsh + ((k & 1) ? nh : 0);
-    const double* t = g.T2 + table_offset(N, m, nh) + k;
-    int p = p0;
-#pragma unroll 4
-    for (; p + 1 < p1; p += 2) {
-      const double t0 = t[(int64_t)p * L];
-      const double t1 = t[(int64_t)(p + 1) * L];
-      const double2 w0 = Ws[p], w1 = Ws[p + 1];
-      ax = fma(t0, w0.x, ax);
-      ay = fma(t0, w0.y, ay);
-      bx = fma(t1, w1.x, bx);
-      by = fma(t1, w1.y, by);
-    }
-    if (p < p1) {
-      const double t0 = t[(int64_t)p * L];
-      const double2 w0 = Ws[p];
-      ax = fma(t0, w0.x, ax);
-      ay = fma(t0, w0.y, ay);
+    // this degree tile's block of the table: rows p of 64 degrees, contiguous
+    const TT* t = analysis_table<TT>(g) + g.t2off[m] + (int64_t)tile * nh * kTile + lane;
+    // batches of kBatch latitudes; the next batch's table loads are issued
+    // before the current batch's FMAs
+    TT tn[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) tn[u] = (p0 + u < p1) ? t[(int64_t)(p0 + u) * kTile] : TT(0);
+    for (int pb = p0; pb < p1; pb += kBatch) {
+      TT tc[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) tc[u] = tn[u];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int p = pb + kBatch + u;
+        tn[u] = (p < p1) ? t[(int64_t)p * kTile] : TT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; u += 2) {
+        const int p = pb + u;
+        if (p < p1) {
+          const double2 w0 = Ws[p];
+          ax = fma(tc[u], (TT)w0.x, ax);
+          ay = fma(tc[u], (TT)w0.y, ay);
+        }
+        if (p + 1 < p1) {
+          const double2 w1 = Ws[p + 1];
+          bx = fma(tc[u + 1], (TT)w1.x, bx);
+          by = fma(tc[u + 1], (TT)w1.y, by);
+        }
+      }
     }
   }
-  red[threadIdx.x] = ax + bx;
-  red[kAnalThreads + threadIdx.x] = ay + by;
+  red[threadIdx.x] = (double)ax + (double)bx;
+  red[kAnalThreads + threadIdx.x] = (double)ay + (double)by;
   __syncthreads();
   if (wave != 0 || l > N) return;
   double sx = 0.0, sy = 0.0;
@@ -91,59 +107,17 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
     sx += red[w * 64 + lane];
     sy += red[kAnalThreads + w * 64 + lane];
   }
-  const double lam = (double)l * (l + 1);
-  double2 n = make_double2(0.0, 0.0);
-  if (l >= 1) {
-    const double r = 1.0 / sqrt(lam);
-    n = make_double2(sx * r, m == 0 ? 0.0 : sy * r);
-  }
-  const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
-  if (out.mode == ANAL_NONLINEAR) {
-    out.n_out[slot] = n;
-    return;
-  }
-  // time-step update
-  double2 rhs = make_double2(0.0, 0.0);
-  if (out.forcing) {
-    const double2 f = out.forcing[slot];
-    rhs = make_double2(out.h * f.x, out.h * f.y);
-  }
-  rhs.x -= out.h * n.x;
-  rhs.y -= out.h * n.y;
-  double2 old[kMaxStepCoef];
-#pragma unroll
-  for (int j = 0; j < kMaxStepCoef; ++j) old[j] = make_double2(0.0, 0.0);
-  const int nold = out.depth;
-#pragma unroll
-  for (int j = 0; j < kMaxStepCoef - 1; ++j)
-    if (j < nold) old[j] = out.hist[(int64_t)j * out.state_count + slot];
-#pragma unroll
-  for (int j = 1; j < kMaxStepCoef; ++j) {
-    if (j < out.ncoef) {
-      rhs.x -= out.c[j] * old[j - 1].x;
-      rhs.y -= out.c[j] * old[j - 1].y;
-    }
-  }
-  const double denom = out.c[0] + out.h * g.nu[b] * lam;
-  double2 a = make_double2(rhs.x / denom, rhs.y / denom);
-  if (l == 0) a = make_double2(0.0, 0.0);
-  if (m == 0) a.y = 0.0;
-  if (out.nonfinite && !(isfinite(a.x) && isfinite(a.y))) *out.nonfinite = 1;
-  if (out.mode == ANAL_STEP_ITER) {
-    out.iter[slot] = a;
-    return;
-  }
-#pragma unroll
-  for (int j = kMaxStepCoef - 1; j >= 1; --j)
-    if (j < nold) out.hist[(int64_t)j * out.state_count + slot] = old[j - 1];
-  out.hist[slot] = a;
+  finish_degree(g, out, b, m, k, sx, sy);
 }
 
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s) {
   dim3 block(kAnalThreads);
   const int ntile = (g.N + 1 + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
-  hipLaunchKernelGGL(k_analysis, grid, block, analysis_lds_bytes(g.nh), s, g, out);
+  if (g.precision == NSE_PREC_FP32)
+    hipLaunchKernelGGL(k_analysis<float>, grid, block, analysis_lds_bytes(g.nh), s, g, out);
+  else
+    hipLaunchKernelGGL(k_analysis<double>, grid, block, analysis_lds_bytes(g.nh), s, g, out);
   return hipGetLastError();
 }
 

@@ -1,10 +1,10 @@
 // Normalised associated Legendre functions Pbar[l,m](mu_p) on the northern
 // Gauss-Legendre nodes (Section 2, eq. (sph_har), with the Condon-Shortley
 // phase and int_{-1}^{1} Pbar^2 dmu = 1 / (2 pi)), computed once per group in
-// FP64 on the GPU and stored twice:
-//   T1[m][l-m][p]  (latitude fastest: read by the synthesis contraction),
-//   T2[m][p][l-m]  (degree fastest:   read by the analysis contraction),
-// for l = m .. N+1 (the sin(theta) d/dtheta fields reach degree N+1).
+// FP64 on the GPU and stored twice (layouts in nse_internal.h):
+//   T1[m][k][p]             (latitude fastest: read by the synthesis),
+//   T2[m][deg tile][p][64]  (degree fastest: read by the analysis),
+// for l = m .. N+1 (k = l - m; the sin(theta) d/dtheta fields reach degree N+1).
 // The southern hemisphere follows from Pbar[l,m](-mu) = (-1)^(l+m) Pbar[l,m](mu).
 #include "nse_internal.h"
 
@@ -25,9 +25,8 @@ __global__ void k_legendre_table(GroupView g, double* T1, double* T2, float* T1f
   const double s = sqrt((1.0 - x) * (1.0 + x));
   double pmm = 0.28209479177387814347;  // 1 / sqrt(4 pi)
   for (int k = 1; k <= m; ++k) pmm *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-  const int64_t base = table_offset(N, m, nh);
-  double* t1 = T1 + base + p;              // stride nh per degree
-  double* t2 = T2 + base + (int64_t)p * L;  // contiguous in degree
+  const int64_t b1 = t1_order_offset(N, m, nh) + p;
+  const int64_t b2 = g.t2off[m] + (int64_t)p * kTile;
   double prev2 = 0.0, prev1 = pmm;
   double a_prev = 0.0;
   for (int k = 0; k < L; ++k) {
@@ -42,11 +41,13 @@ __global__ void k_legendre_table(GroupView g, double* T1, double* T2, float* T1f
       prev2 = prev1;
       prev1 = v;
     }
-    t1[(int64_t)k * nh] = v;
-    t2[k] = v;
+    const int64_t i1 = b1 + (int64_t)k * nh;
+    const int64_t i2 = b2 + (int64_t)(k / kTile) * nh * kTile + (k % kTile);
+    T1[i1] = v;
+    T2[i2] = v;
     if (T1f) {
-      T1f[base + (int64_t)k * nh + p] = (float)v;
-      T2f[base + (int64_t)p * L + k] = (float)v;
+      T1f[i1] = (float)v;
+      T2f[i2] = (float)v;
     }
   }
 }

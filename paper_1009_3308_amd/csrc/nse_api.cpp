@@ -15,7 +15,6 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/nse_sphere.h"
 #include "nse_internal.h"
 
 using namespace nse;
@@ -24,6 +23,7 @@ namespace {
 
 struct Group {
   int N = 0, nlat = 0, nh = 0, M = 0;
+  int precision = NSE_PREC_FP64;
   std::vector<int> members;          // global member indices
   std::vector<int64_t> offsets;      // complex-slot offsets of those members
   std::vector<double> nu;
@@ -31,12 +31,15 @@ struct Group {
   FftPlan plan{};
   double *d_mu = nullptr, *d_w = nullptr, *d_T1 = nullptr, *d_T2 = nullptr;
   float *d_T1f = nullptr, *d_T2f = nullptr;
+  int64_t* d_t2off = nullptr;
+  std::vector<int64_t> t2off;  // [N+2] start of order m in T2
   double2 *d_F = nullptr, *d_W = nullptr, *d_tw = nullptr;
   int64_t* d_off = nullptr;
   double* d_nu = nullptr;
 
   GroupView view() const {
     GroupView g{};
+    g.precision = precision;
     g.N = N;
     g.nlat = nlat;
     g.nh = nh;
@@ -48,6 +51,7 @@ struct Group {
     g.T2 = d_T2;
     g.T1f = d_T1f;
     g.T2f = d_T2f;
+    g.t2off = d_t2off;
     g.F = d_F;
     g.W = d_W;
     g.tw = d_tw;
@@ -171,6 +175,7 @@ void free_group(Group& g) {
   (void)hipFree(g.d_T2);
   (void)hipFree(g.d_T1f);
   (void)hipFree(g.d_T2f);
+  (void)hipFree(g.d_t2off);
   (void)hipFree(g.d_F);
   (void)hipFree(g.d_W);
   (void)hipFree(g.d_tw);
@@ -200,12 +205,21 @@ nse_status build_group(nse_ctx* c, Group& g) {
   NSE_HIP(c, dalloc(&g.d_w, g.nh));
   NSE_HIP(c, hipMemcpy(g.d_mu, g.mu.data(), sizeof(double) * g.nh, hipMemcpyHostToDevice));
   NSE_HIP(c, hipMemcpy(g.d_w, g.w.data(), sizeof(double) * g.nh, hipMemcpyHostToDevice));
-  const int64_t ts = table_size(g.N, g.nh);
-  NSE_HIP(c, dalloc(&g.d_T1, ts));
-  NSE_HIP(c, dalloc(&g.d_T2, ts));
+  const int64_t ts1 = t1_size(g.N, g.nh);
+  g.t2off.assign(g.N + 2, 0);
+  for (int m = 0; m <= g.N; ++m) {
+    const int L = g.N + 2 - m;
+    g.t2off[m + 1] = g.t2off[m] + (int64_t)((L + kTile - 1) / kTile) * g.nh * kTile;
+  }
+  const int64_t ts2 = g.t2off[g.N + 1];
+  NSE_HIP(c, dalloc(&g.d_t2off, g.N + 2));
+  NSE_HIP(c, hipMemcpy(g.d_t2off, g.t2off.data(), sizeof(int64_t) * (g.N + 2),
+                       hipMemcpyHostToDevice));
+  NSE_HIP(c, dalloc(&g.d_T1, ts1));
+  NSE_HIP(c, dalloc(&g.d_T2, ts2));
   if (c->params.precision != NSE_PREC_FP64) {
-    NSE_HIP(c, dalloc(&g.d_T1f, ts));
-    NSE_HIP(c, dalloc(&g.d_T2f, ts));
+    NSE_HIP(c, dalloc(&g.d_T1f, ts1));
+    NSE_HIP(c, dalloc(&g.d_T2f, ts2));
   }
   NSE_HIP(c, dalloc(&g.d_F, (size_t)nb * 4 * g.nlat * (g.N + 1)));
   NSE_HIP(c, dalloc(&g.d_W, (size_t)nb * g.nlat * (g.N + 1)));
@@ -269,18 +283,30 @@ nse_status timed_launch(nse_ctx* c, int kind, F&& launch) {
   return NSE_OK;
 }
 
+// FP64 and FP32 contractions run on the vector units (HBM-bound table streams);
+// the split-bf16 form runs on MFMA.
+hipError_t launch_synth_any(const GroupView& v, const SynthInput& in, int mode, hipStream_t s) {
+  if (v.precision == NSE_PREC_BF16X3) return launch_synthesis_lp(v, in, mode, v.precision, s);
+  return launch_synthesis(v, in, mode, s);
+}
+
+hipError_t launch_anal_any(const GroupView& v, const AnalOutput& out, hipStream_t s) {
+  if (v.precision == NSE_PREC_BF16X3) return launch_analysis_lp(v, out, v.precision, s);
+  return launch_analysis(v, out, s);
+}
+
 // Enqueues one full evaluation chain (synthesis, ring, analysis) for every group.
 nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out) {
   for (auto& g : c->groups) {
     const GroupView v = g.view();
     nse_status s;
     s = timed_launch(c, NSE_KERNEL_SYNTHESIS,
-                     [&] { return launch_synthesis(v, in, SYNTH_NONLINEAR, c->stream); });
+                     [&] { return launch_synth_any(v, in, SYNTH_NONLINEAR, c->stream); });
     if (s != NSE_OK) return s;
     s = timed_launch(c, NSE_KERNEL_RING,
                      [&] { return launch_ring(v, g.plan, SYNTH_NONLINEAR, nullptr, c->stream); });
     if (s != NSE_OK) return s;
-    s = timed_launch(c, NSE_KERNEL_ANALYSIS, [&] { return launch_analysis(v, out, c->stream); });
+    s = timed_launch(c, NSE_KERNEL_ANALYSIS, [&] { return launch_anal_any(v, out, c->stream); });
     if (s != NSE_OK) return s;
   }
   return NSE_OK;
@@ -373,8 +399,6 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
     return init_fail(NSE_ERR_ARG, "unknown flag bits");
   if (!is_finite(P.omega)) return init_fail(NSE_ERR_ARG, "omega must be finite");
   if (!is_finite(P.dt) || !(P.dt > 0.0)) return init_fail(NSE_ERR_ARG, "dt must be finite and > 0");
-  if (P.precision != NSE_PREC_FP64)
-    return init_fail(NSE_ERR_UNSUPPORTED, "reduced-precision contractions are not built yet");
 
   std::vector<nse_member> mem(members, members + n_members);
   for (int i = 0; i < n_members; ++i) {
@@ -409,7 +433,8 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
     }
     if (synthesis_lds_bytes(m.N) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
-        analysis_lds_bytes((m.nlat + 1) / 2) > 65536) {
+        analysis_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
+        analysis_lp_lds_bytes((m.nlat + 1) / 2) > 65536) {
       snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,
                m.N);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
@@ -433,6 +458,7 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
       if (c->groups[j].N == mem[i].N && c->groups[j].nlat == mem[i].nlat) gi = (int)j;
     if (gi < 0) {
       Group g;
+      g.precision = P.precision;
       g.N = mem[i].N;
       g.nlat = mem[i].nlat;
       fft_factor(2 * g.nlat, g.plan);
@@ -599,7 +625,7 @@ nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out) {
   for (size_t i = 0; i < ctx->members.size(); ++i) {
     const Group& g = ctx->groups[ctx->member_group[i]];
     const GroupView v = g.member_view(ctx->member_index[i]);
-    NSE_HIP(ctx, launch_synthesis(v, in, SYNTH_GRID, ctx->stream));
+    NSE_HIP(ctx, launch_synth_any(v, in, SYNTH_GRID, ctx->stream));
     NSE_HIP(ctx, launch_ring(v, g.plan, SYNTH_GRID, grid_out + goff, ctx->stream));
     goff += (int64_t)3 * g.nlat * g.M;
   }
@@ -614,7 +640,7 @@ nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m, double* 
   const Group& g = ctx->groups[ctx->member_group[member]];
   if (m < 0 || m > g.N) return fail(ctx, NSE_ERR_ARG, "order m = %d outside 0..%d", m, g.N);
   const size_t count = (size_t)(g.N + 2 - m) * g.nh;
-  NSE_HIP(ctx, hipMemcpyAsync(out, g.d_T1 + table_offset(g.N, m, g.nh), sizeof(double) * count,
+  NSE_HIP(ctx, hipMemcpyAsync(out, g.d_T1 + t1_order_offset(g.N, m, g.nh), sizeof(double) * count,
                               hipMemcpyDeviceToDevice, ctx->stream));
   return NSE_OK;
 }

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "nse_sphere.h"
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -32,23 +34,30 @@ __host__ __device__ inline int xcd_grid(int items, int chunk) {
 __host__ __device__ inline int64_t coeff_offset(int N, int m) {
   return (int64_t)m * (2 * N + 3 - m) / 2;
 }
-// Start of order m in a table that stores l = m .. N+1 for nh latitudes.
-__host__ __device__ inline int64_t table_offset(int N, int m, int nh) {
+// Legendre tables, l = m .. N+1 (L = N + 2 - m degrees for order m, k = l - m):
+//   T1[m][k][p]                        (synthesis; latitude fastest, row stride nh)
+//   T2[m][deg tile][p][64 degrees]     (analysis; ceil(L/64) tiles of 64 degrees,
+//                                       each a contiguous block streamed by one
+//                                       workgroup; orders start at t2off[m])
+constexpr int kTile = 64;
+__host__ __device__ inline int64_t t1_order_offset(int N, int m, int nh) {
   return (int64_t)nh * ((int64_t)m * (2 * N + 5 - m) / 2);
 }
-__host__ __device__ inline int64_t table_size(int N, int nh) {
+__host__ __device__ inline int64_t t1_size(int N, int nh) {
   return (int64_t)nh * ((int64_t)(N + 1) * (N + 4) / 2);
 }
 
 // Device view of one truncation group (members sharing N and nlat).
 struct GroupView {
   int N, nlat, nh, M, nb;   // nh = northern latitudes incl. the equator if nlat is odd
+  int precision;            // NSE_PREC_* of the Legendre contractions
   const double* mu;         // [nh] Gauss-Legendre nodes, descending
   const double* w;          // [nh]
-  const double* T1;         // [m][l-m][p]  FP64, l = m..N+1
-  const double* T2;         // [m][p][l-m]  FP64, l = m..N+1
+  const double* T1;         // FP64 synthesis table (layouts above)
+  const double* T2;         // FP64 analysis table
   const float* T1f;         // FP32 copies (precision modes), may be null
   const float* T2f;
+  const int64_t* t2off;     // [N+2] start of order m in T2 (element units)
   double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
   double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
   const double2* tw;        // [M] exp(-2 pi i k / M)
@@ -94,11 +103,29 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s);
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s);
+hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
+                               hipStream_t s);
+hipError_t launch_analysis_lp(const GroupView& g, const AnalOutput& out, int prec, hipStream_t s);
+
+template <typename TT>
+__host__ __device__ inline const TT* synthesis_table(const GroupView& g);
+template <>
+__host__ __device__ inline const double* synthesis_table<double>(const GroupView& g) { return g.T1; }
+template <>
+__host__ __device__ inline const float* synthesis_table<float>(const GroupView& g) { return g.T1f; }
+template <typename TT>
+__host__ __device__ inline const TT* analysis_table(const GroupView& g);
+template <>
+__host__ __device__ inline const double* analysis_table<double>(const GroupView& g) { return g.T2; }
+template <>
+__host__ __device__ inline const float* analysis_table<float>(const GroupView& g) { return g.T2f; }
 
 // Dynamic LDS of the launches (validated against 64 KiB at init).
 size_t synthesis_lds_bytes(int N);
 size_t ring_lds_bytes(int M);
 size_t analysis_lds_bytes(int nh);
+size_t synthesis_lp_lds_bytes(int N);
+size_t analysis_lp_lds_bytes(int nh);
 
 // Host numerics.
 void gauss_legendre(int n, std::vector<double>& mu, std::vector<double>& w);

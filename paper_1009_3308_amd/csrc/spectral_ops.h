@@ -1,0 +1,164 @@
+// Spectral-side pieces shared by the FP64 and reduced-precision contraction
+// kernels: the per-order input and coefficient panels of the synthesis, and
+// the per-degree epilogue of the analysis (post-scaling and time step).
+#pragma once
+
+#include "nse_internal.h"
+
+namespace nse {
+
+// alpha[l, m] for l = m..N into a[k], k = l - m (sum of the input sources,
+// e.g. the extrapolated predictor); zero for l = 0 and for k up to L, where
+// L = N + 2 - m is the number of degrees the panels reach (m..N+1).
+__device__ inline void load_order(double2* a, const GroupView& g, const SynthInput& in, int b,
+                                  int m, int L) {
+  const int N = g.N;
+  const int64_t base = g.off[b] + coeff_offset(N, m);
+  for (int k = threadIdx.x; k < L + 1; k += blockDim.x) {
+    const int l = m + k;
+    double2 v = make_double2(0.0, 0.0);
+    if (l >= 1 && l <= N) {
+#pragma unroll
+      for (int i = 0; i < kMaxSources; ++i) {
+        if (i < in.nsrc) {
+          const double2 x = in.src[i][base + k];
+          v.x += in.coef[i] * x.x;
+          v.y += in.coef[i] * x.y;
+        }
+      }
+      if (m == 0) v.y = 0.0;
+    }
+    a[k] = v;
+  }
+}
+
+// The four coefficient panels of order m (value of field f at k = l - m < L):
+// with psi = lambda^(-1/2) alpha and the absolute vorticity zeta_a =
+// lambda^(1/2) alpha (+ 2 Omega sqrt(4 pi / 3) at (1, 0)),
+//   f0 = i m psi,  f1 = sin(theta) dpsi/dtheta,  f2 = sin(theta) dzeta_a/dtheta,  f3 = i m zeta_a,
+// where sin(theta) d/dtheta acts on the coefficients by
+//   (l-1) e(l) c[l-1] - (l+2) e(l+1) c[l+1],  e(l) = sqrt((l^2 - m^2) / (4 l^2 - 1)),
+// from sin(theta) dPbar[l,m]/dtheta = l e(l+1) Pbar[l+1,m] - (l+1) e(l) Pbar[l-1,m].
+// Grid-output mode: f0 = i m psi, f1 = sin(theta) dpsi/dtheta, f2 = zeta, f3 = 0.
+// a[] holds alpha[m + k] for k = 0..L (zero outside 1..N), see load_order.
+__device__ inline double2 panel_value(const double2* a, int N, int m, int k, int f, int mode,
+                                      double coriolis) {
+  const int l = m + k;
+  const double dl = (double)l, dm = (double)m;
+  // scale of psi (s = -1) or zeta_a (s = +1) at offset kk
+  auto coef = [&](int kk, bool zeta) -> double2 {
+    const int ll = m + kk;
+    if (kk < 0 || ll < 1 || ll > N) return make_double2(0.0, 0.0);
+    const double lam = (double)ll * (ll + 1);
+    const double r = zeta ? sqrt(lam) : 1.0 / sqrt(lam);
+    double2 z = make_double2(a[kk].x * r, a[kk].y * r);
+    if (zeta && mode == SYNTH_NONLINEAR && m == 0 && ll == 1) z.x += coriolis;
+    return z;
+  };
+  if (f == 0 || (f == 3 && mode == SYNTH_NONLINEAR)) {
+    const double2 c = coef(k, f == 3);
+    return make_double2(-dm * c.y, dm * c.x);  // i m c
+  }
+  if (f == 3) return make_double2(0.0, 0.0);
+  if (f == 2 && mode != SYNTH_NONLINEAR) return coef(k, true);
+  const bool zeta = (f == 2);
+  const double e_l = (l > m) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
+  const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
+  const double cm = (dl - 1.0) * e_l, cp = (dl + 2.0) * e_l1;
+  const double2 lo = coef(k - 1, zeta), hi = coef(k + 1, zeta);
+  return make_double2(cm * lo.x - cp * hi.x, cm * lo.y - cp * hi.y);
+}
+
+// All four panels of order m into pan[4k + f], k < L (one degree per thread,
+// the neighbouring coefficients shared by the four fields).
+__device__ inline void build_panel(double2* pan, const double2* a, int N, int m, int L, int mode,
+                                   double coriolis) {
+  const double dm = (double)m;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    const int l = m + k;
+    const double dl = (double)l;
+    double2 ps[3], zs[3];  // psi and zeta_a at k-1, k, k+1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int kk = k - 1 + d, ll = m + kk;
+      ps[d] = zs[d] = make_double2(0.0, 0.0);
+      if (kk >= 0 && ll >= 1 && ll <= N) {
+        const double lam = (double)ll * (ll + 1);
+        const double sq = sqrt(lam), r = 1.0 / sq;
+        ps[d] = make_double2(a[kk].x * r, a[kk].y * r);
+        zs[d] = make_double2(a[kk].x * sq, a[kk].y * sq);
+        if (mode == SYNTH_NONLINEAR && m == 0 && ll == 1) zs[d].x += coriolis;
+      }
+    }
+    const double e_l = (l > m) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
+    const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
+    const double cm = (dl - 1.0) * e_l, cp = (dl + 2.0) * e_l1;
+    pan[4 * k + 0] = make_double2(-dm * ps[1].y, dm * ps[1].x);
+    pan[4 * k + 1] = make_double2(cm * ps[0].x - cp * ps[2].x, cm * ps[0].y - cp * ps[2].y);
+    if (mode == SYNTH_NONLINEAR) {
+      pan[4 * k + 2] = make_double2(cm * zs[0].x - cp * zs[2].x, cm * zs[0].y - cp * zs[2].y);
+      pan[4 * k + 3] = make_double2(-dm * zs[1].y, dm * zs[1].x);
+    } else {
+      pan[4 * k + 2] = zs[1];
+      pan[4 * k + 3] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Degree l = m + k of the analysis: s = sum_p Pbar[l,m](mu_p) (We or Wo).
+// n[l,m] = lambda_l^(-1/2) s (zero at l = 0, real at m = 0); then either
+// stored (nonlinear mode) or used in the NDF step
+//   alpha_new = (h (f - n) - sum_{j>=1} c_j hist[j-1]) / (c_0 + h nu lambda_l),
+// written as the next fixed-point iterate or, on the last sweep, to hist[0]
+// after rotating hist[j] <- hist[j-1] (eq. (ode_disc), eq. (stok_eig)).
+__device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, int b, int m,
+                                     int k, double sx, double sy) {
+  const int l = m + k;
+  const double lam = (double)l * (l + 1);
+  double2 n = make_double2(0.0, 0.0);
+  if (l >= 1) {
+    const double r = 1.0 / sqrt(lam);
+    n = make_double2(sx * r, m == 0 ? 0.0 : sy * r);
+  }
+  const int64_t slot = g.off[b] + coeff_offset(g.N, m) + k;
+  if (out.mode == ANAL_NONLINEAR) {
+    out.n_out[slot] = n;
+    return;
+  }
+  double2 rhs = make_double2(0.0, 0.0);
+  if (out.forcing) {
+    const double2 f = out.forcing[slot];
+    rhs = make_double2(out.h * f.x, out.h * f.y);
+  }
+  rhs.x -= out.h * n.x;
+  rhs.y -= out.h * n.y;
+  double2 old[kMaxStepCoef];
+#pragma unroll
+  for (int j = 0; j < kMaxStepCoef; ++j) old[j] = make_double2(0.0, 0.0);
+  const int nold = out.depth;
+#pragma unroll
+  for (int j = 0; j < kMaxStepCoef - 1; ++j)
+    if (j < nold) old[j] = out.hist[(int64_t)j * out.state_count + slot];
+#pragma unroll
+  for (int j = 1; j < kMaxStepCoef; ++j) {
+    if (j < out.ncoef) {
+      rhs.x -= out.c[j] * old[j - 1].x;
+      rhs.y -= out.c[j] * old[j - 1].y;
+    }
+  }
+  const double denom = out.c[0] + out.h * g.nu[b] * lam;
+  double2 a = make_double2(rhs.x / denom, rhs.y / denom);
+  if (l == 0) a = make_double2(0.0, 0.0);
+  if (m == 0) a.y = 0.0;
+  if (out.nonfinite && !(isfinite(a.x) && isfinite(a.y))) *out.nonfinite = 1;
+  if (out.mode == ANAL_STEP_ITER) {
+    out.iter[slot] = a;
+    return;
+  }
+#pragma unroll
+  for (int j = kMaxStepCoef - 1; j >= 1; --j)
+    if (j < nold) out.hist[(int64_t)j * out.state_count + slot] = old[j - 1];
+  out.hist[slot] = a;
+}
+
+}  // namespace nse
