@@ -21,7 +21,8 @@ Z[l,m] = (l(l+1))^(-1/2) Curl Y[l,m] and u = Curl psi.
 
 Seeds used by the tests and the benchmark:
     1 initial state, 2 forcing (scale 1e-2), 3 target state, 4 finite-difference
-    directions, 5 ensemble viscosities, 100+i ensemble member i.
+    directions, 5 ensemble viscosities, 6 adjoint cotangents (flat spectrum),
+    100+i ensemble member i.
 """
 from __future__ import annotations
 
@@ -32,6 +33,7 @@ SEED_FORCING = 2
 SEED_TARGET = 3
 SEED_DIRECTIONS = 4
 SEED_ENSEMBLE_NU = 5
+SEED_COTANGENT = 6
 SEED_MEMBER0 = 100
 
 
@@ -94,6 +96,18 @@ def target_state(N: int) -> np.ndarray:
 def directions(N: int, count: int) -> np.ndarray:
     """count seeded directions of the same spectral shape, shape [count, slots]."""
     return np.stack([spectrum(SEED_DIRECTIONS * 1000 + i, N, 1.0) for i in range(count)])
+
+
+def cotangent(N: int, index: int = 0) -> np.ndarray:
+    """A seeded cotangent with unit-variance entries at every degree (no decay),
+    zero at l = 0 and real at m = 0, for adjoint tests."""
+    rng = np.random.default_rng(SEED_COTANGENT * 1000 + index)
+    ls, ms = degrees_orders(N)
+    z = rng.standard_normal((len(ls), 2))
+    out = (z[:, 0] + 1j * z[:, 1]).astype(np.complex128)
+    out[ms == 0] = z[ms == 0, 0]
+    out[ls == 0] = 0.0
+    return out
 
 
 def ensemble_viscosities(count: int, lo: float = 1e-5, hi: float = 1e-3) -> np.ndarray:

@@ -25,6 +25,7 @@ SOURCES = [
     "ring_fft.hip",
     "analysis.hip",
     "contract_lp.hip",
+    "adjoint.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -1,0 +1,223 @@
+// Adjoint (vector-Jacobian product on the stored real doubles) of the
+// synthesis and of the spectral prologue of the nonlinear term, and the
+// element-wise parts of the adjoint of one NDF_p step (eq. (ode_disc)).
+//
+// Synthesis^T: the synthesis computes G_f(m, lat) = sum_k Pbar[m+k, m](mu_lat)
+// P_f(m, k) for the four panel fields (complex-linear with real coefficients),
+// so its transpose is the unweighted Legendre analysis
+//   Pbar_f(m, k) = sum_lat Pbar[m+k, m](mu_lat) Gbar_f(lat, m),   k < N+2-m,
+// folded over latitude pairs (the equator ring of an odd rule counted once).
+// Prologue^T: the panels are f0 = i m psi, f1 = S psi, f2 = S zeta_a,
+// f3 = i m zeta_a with psi = lambda^(-1/2) alpha, zeta_a = lambda^(1/2) alpha
+// (+ constant) and S c[k] = cm(k) c[k-1] - cp(k) c[k+1], cm(k) = (l-1) e(l),
+// cp(k) = (l+2) e(l+1), l = m + k; so
+//   psi_bar[j]  = -i m f0_bar[j] + cm(j+1) f1_bar[j+1] - cp(j-1) f1_bar[j-1],
+//   zeta_bar[j] = -i m f3_bar[j] + cm(j+1) f2_bar[j+1] - cp(j-1) f2_bar[j-1],
+//   alpha_bar[j] = lambda^(-1/2) psi_bar[j] + lambda^(1/2) zeta_bar[j],
+// zero at l = 0 and real at m = 0 (those inputs are fixed to zero).
+#include "spectral_ops.h"
+
+namespace nse {
+
+constexpr int kAdjWaves = 4;
+constexpr int kAdjThreads = 64 * kAdjWaves;
+
+size_t synthesis_adjoint_lds_bytes(int nh) {
+  // folded cotangents [4 fields][2 parities][nh], reused for the cross-wave sums
+  const size_t fold = sizeof(double2) * 8 * (size_t)nh;
+  const size_t red = sizeof(double) * 8 * kAdjThreads;
+  return fold > red ? fold : red;
+}
+
+// One workgroup of four waves per (order m, tile of 64 degrees k < N+2-m,
+// member); one thread per degree, each wave summing a quarter of the northern
+// latitudes of T2[m][tile][p][64].
+__global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) {
+  const int N = g.N, nh = g.nh, nlat = g.nlat;
+  const int ntile = (N + 2 + 63) / 64;
+  const int m = blockIdx.x / ntile;
+  const int tile = blockIdx.x - m * ntile;
+  const int L = N + 2 - m;
+  if (tile * 64 >= L) return;  // uniform across the workgroup
+  const int b = blockIdx.y;
+  extern __shared__ double2 fsh[];  // [f][parity][nh]
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + m;  // Fbar[b][f][lat][m]
+  for (int i = threadIdx.x; i < 4 * nh; i += blockDim.x) {
+    const int f = i / nh, p = i - f * nh;
+    const int ps = nlat - 1 - p;
+    const double2 gn = Gb[f * fstride + (int64_t)p * (N + 1)];
+    double2 we = gn, wo = make_double2(0.0, 0.0);
+    if (ps != p) {
+      const double2 gs = Gb[f * fstride + (int64_t)ps * (N + 1)];
+      we = make_double2(gn.x + gs.x, gn.y + gs.y);
+      wo = make_double2(gn.x - gs.x, gn.y - gs.y);
+    }
+    fsh[(2 * f) * nh + p] = we;
+    fsh[(2 * f + 1) * nh + p] = wo;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = tile * 64 + lane;
+  const int pq = (nh + kAdjWaves - 1) / kAdjWaves;
+  const int p0 = wave * pq, p1 = min(nh, p0 + pq);
+  double acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+  if (k < L) {
+    const int par = k & 1;
+    const double* t = g.T2 + g.t2off[m] + (int64_t)tile * nh * kTile + lane;
+    for (int p = p0; p < p1; ++p) {
+      const double tv = t[(int64_t)p * kTile];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double2 w = fsh[(2 * f + par) * nh + p];
+        acc[2 * f + 0] = fma(tv, w.x, acc[2 * f + 0]);
+        acc[2 * f + 1] = fma(tv, w.y, acc[2 * f + 1]);
+      }
+    }
+  }
+  __syncthreads();  // the folded cotangents are no longer needed
+  double* red = reinterpret_cast<double*>(fsh);  // [8][kAdjThreads]
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[i * kAdjThreads + threadIdx.x] = acc[i];
+  __syncthreads();
+  if (wave != 0 || k >= L) return;
+  double2* out = g.Pbar + (((int64_t)b * (N + 1) + m) * (N + 2) + k) * 4;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int w = 0; w < kAdjWaves; ++w) {
+      sx += red[(2 * f) * kAdjThreads + w * 64 + lane];
+      sy += red[(2 * f + 1) * kAdjThreads + w * 64 + lane];
+    }
+    out[f] = make_double2(sx, sy);
+  }
+}
+
+// One workgroup per (order m, member); one thread per degree l = m..N.
+__global__ __launch_bounds__(256) void k_prep_adjoint(GroupView g, double2* alpha_bar) {
+  const int N = g.N;
+  const int m = blockIdx.x, b = blockIdx.y;
+  const int L = N + 2 - m;
+  const double dm = (double)m;
+  const double2* P = g.Pbar + ((int64_t)b * (N + 1) + m) * (N + 2) * 4;  // [k][f]
+  auto e_of = [&](int l) -> double {
+    return (l > m) ? sqrt(((double)l * l - dm * dm) / (4.0 * (double)l * l - 1.0)) : 0.0;
+  };
+  for (int k = threadIdx.x; k <= N - m; k += blockDim.x) {
+    const int l = m + k;
+    double2 out = make_double2(0.0, 0.0);
+    if (l >= 1) {
+      double2 psib = make_double2(dm * P[4 * k + 0].y, -dm * P[4 * k + 0].x);   // -i m f0_bar
+      double2 zetb = make_double2(dm * P[4 * k + 3].y, -dm * P[4 * k + 3].x);   // -i m f3_bar
+      if (k + 1 < L) {
+        const double cmn = (double)(l + 1 - 1) * e_of(l + 1);  // cm(k+1)
+        psib.x += cmn * P[4 * (k + 1) + 1].x;
+        psib.y += cmn * P[4 * (k + 1) + 1].y;
+        zetb.x += cmn * P[4 * (k + 1) + 2].x;
+        zetb.y += cmn * P[4 * (k + 1) + 2].y;
+      }
+      if (k >= 1) {
+        const double cpp = (double)(l - 1 + 2) * e_of(l);  // cp(k-1)
+        psib.x -= cpp * P[4 * (k - 1) + 1].x;
+        psib.y -= cpp * P[4 * (k - 1) + 1].y;
+        zetb.x -= cpp * P[4 * (k - 1) + 2].x;
+        zetb.y -= cpp * P[4 * (k - 1) + 2].y;
+      }
+      const double sq = sqrt((double)l * (l + 1));
+      out = make_double2(psib.x / sq + zetb.x * sq, m == 0 ? 0.0 : psib.y / sq + zetb.y * sq);
+    }
+    alpha_bar[g.off[b] + coeff_offset(N, m) + k] = out;
+  }
+}
+
+hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s) {
+  const int ntile = (g.N + 2 + 63) / 64;
+  dim3 grid((g.N + 1) * ntile, g.nb);
+  hipLaunchKernelGGL(k_synthesis_adjoint, grid, dim3(kAdjThreads),
+                     synthesis_adjoint_lds_bytes(g.nh), s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream_t s) {
+  dim3 grid(g.N + 1, g.nb);
+  hipLaunchKernelGGL(k_prep_adjoint, grid, dim3(256), 0, s, g, alpha_bar);
+  return hipGetLastError();
+}
+
+// Element-wise part of the adjoint of one step, before the nonlinear adjoint:
+// with r = hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0),
+//   n_bar = -h r,  hbar_in[j] = hbar_out[j+1] - c_{j+1} r   (j = 0 .. depth-1),
+// written in place over hist_bar.
+__global__ __launch_bounds__(256) void k_step_adjoint_pre(GroupView g, AnalOutput st,
+                                                          double2* hist_bar, double2* nbar) {
+  const int N = g.N;
+  const int m = blockIdx.x, b = blockIdx.z;
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k > N - m) return;
+  const int l = m + k;
+  const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
+  const double lam = (double)l * (l + 1);
+  const double denom = st.c[0] + st.h * g.nu[b] * lam;
+  double2 r = hist_bar[slot];
+  r = make_double2(r.x / denom, r.y / denom);
+  if (l == 0) r = make_double2(0.0, 0.0);
+  if (m == 0) r.y = 0.0;
+  nbar[slot] = make_double2(-st.h * r.x, -st.h * r.y);
+  double2 hb[kMaxStepCoef];
+#pragma unroll
+  for (int j = 0; j < kMaxStepCoef; ++j) {
+    hb[j] = make_double2(0.0, 0.0);
+    if (j + 1 < st.depth) hb[j] = hist_bar[(int64_t)(j + 1) * st.state_count + slot];
+    if (j + 1 < st.ncoef) {
+      hb[j].x -= st.c[j + 1] * r.x;
+      hb[j].y -= st.c[j + 1] * r.y;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxStepCoef; ++j)
+    if (j < st.depth) hist_bar[(int64_t)j * st.state_count + slot] = hb[j];
+}
+
+// After the nonlinear adjoint at the predictor: hbar_in[i] += pi_i alpha_bar.
+__global__ __launch_bounds__(256) void k_step_adjoint_post(GroupView g, SynthInput pred,
+                                                           int64_t state_count,
+                                                           double2* hist_bar,
+                                                           const double2* abar) {
+  const int N = g.N;
+  const int m = blockIdx.x, b = blockIdx.z;
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k > N - m) return;
+  const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
+  const double2 a = abar[slot];
+#pragma unroll
+  for (int i = 0; i < kMaxSources; ++i) {
+    if (i < pred.nsrc) {
+      double2 h = hist_bar[(int64_t)i * state_count + slot];
+      h.x += pred.coef[i] * a.x;
+      h.y += pred.coef[i] * a.y;
+      hist_bar[(int64_t)i * state_count + slot] = h;
+    }
+  }
+}
+
+hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, double2* hist_bar,
+                                   double2* nbar, hipStream_t s) {
+  dim3 grid(g.N + 1, (g.N + 1 + 255) / 256, g.nb);
+  hipLaunchKernelGGL(k_step_adjoint_pre, grid, dim3(256), 0, s, g, st, hist_bar, nbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint_post(const GroupView& g, const SynthInput& pred,
+                                    int64_t state_count, double2* hist_bar, const double2* abar,
+                                    hipStream_t s) {
+  dim3 grid(g.N + 1, (g.N + 1 + 255) / 256, g.nb);
+  hipLaunchKernelGGL(k_step_adjoint_post, grid, dim3(256), 0, s, g, pred, state_count, hist_bar,
+                     abar);
+  return hipGetLastError();
+}
+
+}  // namespace nse

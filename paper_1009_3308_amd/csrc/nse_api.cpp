@@ -34,6 +34,7 @@ struct Group {
   int64_t* d_t2off = nullptr;
   std::vector<int64_t> t2off;  // [N+2] start of order m in T2
   double2 *d_F = nullptr, *d_W = nullptr, *d_tw = nullptr;
+  double2 *d_Fa = nullptr, *d_Fbar = nullptr, *d_Pbar = nullptr;  // adjoint, allocated on demand
   int64_t* d_off = nullptr;
   double* d_nu = nullptr;
 
@@ -53,6 +54,9 @@ struct Group {
     g.T2f = d_T2f;
     g.t2off = d_t2off;
     g.F = d_F;
+    g.Fa = d_Fa;
+    g.Fbar = d_Fbar;
+    g.Pbar = d_Pbar;
     g.W = d_W;
     g.tw = d_tw;
     g.off = d_off;
@@ -88,6 +92,7 @@ struct nse_ctx {
   int64_t state_count = 0;
   double2* d_iter = nullptr;
   int* d_flag = nullptr;
+  double2 *d_nbar = nullptr, *d_abar = nullptr;  // adjoint step temporaries, on demand
   std::string err;
   // captured step chunks keyed by (hist, forcing, chunk length)
   std::map<std::tuple<const void*, const void*, int>, GraphEntry> graphs;
@@ -178,6 +183,9 @@ void free_group(Group& g) {
   (void)hipFree(g.d_t2off);
   (void)hipFree(g.d_F);
   (void)hipFree(g.d_W);
+  (void)hipFree(g.d_Fa);
+  (void)hipFree(g.d_Fbar);
+  (void)hipFree(g.d_Pbar);
   (void)hipFree(g.d_tw);
   (void)hipFree(g.d_off);
   (void)hipFree(g.d_nu);
@@ -348,6 +356,39 @@ nse_status enqueue_step(nse_ctx* c, double2* hist, const double2* forcing, int64
   return NSE_OK;
 }
 
+// Buffers of the adjoint (four forward fields plus the analysis cotangent,
+// the field-spectrum cotangents and the panel cotangents), allocated on the
+// first adjoint call.
+nse_status ensure_adjoint_buffers(nse_ctx* c) {
+  for (auto& g : c->groups) {
+    if (g.d_Fa) continue;
+    const size_t nb = g.members.size();
+    const size_t fs = (size_t)g.nlat * (g.N + 1);
+    NSE_HIP(c, dalloc(&g.d_Fa, nb * 5 * fs));
+    NSE_HIP(c, dalloc(&g.d_Fbar, nb * 4 * fs));
+    NSE_HIP(c, dalloc(&g.d_Pbar, nb * (size_t)(g.N + 1) * (g.N + 2) * 4));
+  }
+  if (!c->d_nbar) NSE_HIP(c, dalloc(&c->d_nbar, (size_t)c->state_count));
+  if (!c->d_abar) NSE_HIP(c, dalloc(&c->d_abar, (size_t)c->state_count));
+  return NSE_OK;
+}
+
+// alpha_bar = J^T n_bar at the synthesis input `in` (always FP64 tables):
+// recompute the forward spectra with the analysis cotangent as a fifth field,
+// then the transposed ring, synthesis and prologue.
+nse_status enqueue_nonlinear_adjoint(nse_ctx* c, SynthInput in, const double2* n_bar,
+                                     double2* alpha_bar) {
+  in.adj = n_bar;
+  for (auto& g : c->groups) {
+    const GroupView v = g.view();
+    NSE_HIP(c, launch_synthesis(v, in, SYNTH_ADJ, c->stream));
+    NSE_HIP(c, launch_ring_adjoint(v, g.plan, c->stream));
+    NSE_HIP(c, launch_synthesis_adjoint(v, c->stream));
+    NSE_HIP(c, launch_prep_adjoint(v, alpha_bar, c->stream));
+  }
+  return NSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -432,7 +473,8 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
                "member %d: M = %d must be <= %d and factor into 2, 3 and 5", i, 2 * m.nlat, kMaxM);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
     }
-    if (synthesis_lds_bytes(m.N) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
+    if (synthesis_lds_bytes(m.N, 5) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
+        synthesis_adjoint_lds_bytes((m.nlat + 1) / 2) > 65536 ||
         analysis_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
         analysis_lp_lds_bytes((m.nlat + 1) / 2) > 65536) {
       snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,
@@ -505,6 +547,8 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   for (auto& g : ctx->groups) free_group(g);
   (void)hipFree(ctx->d_iter);
   (void)hipFree(ctx->d_flag);
+  (void)hipFree(ctx->d_nbar);
+  (void)hipFree(ctx->d_abar);
   delete ctx;
   return NSE_OK;
 }
@@ -602,16 +646,53 @@ nse_status nse_nonlinear_adjoint(nse_ctx* ctx, const double* alpha, const double
                                  double* alpha_bar) {
   if (!ctx) return NSE_ERR_ARG;
   if (!alpha || !n_bar || !alpha_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
-  return fail(ctx, NSE_ERR_UNSUPPORTED, "adjoint not built yet");
+  if (alpha_bar == alpha || alpha_bar == n_bar)
+    return fail(ctx, NSE_ERR_ARG, "alpha_bar may not alias alpha or n_bar");
+  nse_status s = ensure_adjoint_buffers(ctx);
+  if (s != NSE_OK) return s;
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = (const double2*)alpha;
+  in.coef[0] = 1.0;
+  in.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  return enqueue_nonlinear_adjoint(ctx, in, (const double2*)n_bar, (double2*)alpha_bar);
 }
 
 nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forcing, int64_t step,
                             double* hist_bar) {
   if (!ctx) return NSE_ERR_ARG;
-  (void)forcing;
+  (void)forcing;  // the forcing enters affinely and is not differentiated
   if (!hist || !hist_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  if (hist == hist_bar) return fail(ctx, NSE_ERR_ARG, "hist and hist_bar may not alias");
   if (step < 0) return fail(ctx, NSE_ERR_ARG, "step must be >= 0");
-  return fail(ctx, NSE_ERR_UNSUPPORTED, "adjoint not built yet");
+  if (ctx->params.newton_iters != 1)
+    return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
+  nse_status s = ensure_adjoint_buffers(ctx);
+  if (s != NSE_OK) return s;
+  std::vector<double> cc, pi;
+  step_scheme(ctx->params.order, step, cc, pi);
+  AnalOutput st{};
+  st.state_count = ctx->state_count;
+  st.depth = ctx->params.order + 1;
+  st.ncoef = (int)cc.size();
+  for (int j = 0; j < st.ncoef; ++j) st.c[j] = cc[j];
+  st.h = ctx->params.dt;
+  SynthInput pred{};
+  pred.nsrc = (int)pi.size();
+  for (int i = 0; i < pred.nsrc; ++i) {
+    pred.src[i] = (const double2*)hist + (int64_t)i * ctx->state_count;
+    pred.coef[i] = pi[i];
+  }
+  pred.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  double2* hb = (double2*)hist_bar;
+  for (auto& g : ctx->groups)
+    NSE_HIP(ctx, launch_step_adjoint_pre(g.view(), st, hb, ctx->d_nbar, ctx->stream));
+  s = enqueue_nonlinear_adjoint(ctx, pred, ctx->d_nbar, ctx->d_abar);
+  if (s != NSE_OK) return s;
+  for (auto& g : ctx->groups)
+    NSE_HIP(ctx, launch_step_adjoint_post(g.view(), pred, ctx->state_count, hb, ctx->d_abar,
+                                          ctx->stream));
+  return NSE_OK;
 }
 
 nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out) {

@@ -59,6 +59,9 @@ struct GroupView {
   const float* T2f;
   const int64_t* t2off;     // [N+2] start of order m in T2 (element units)
   double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
+  double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
+  double2* Fbar;            // adjoint: [nb][4][nlat][N+1] cotangents of the field spectra
+  double2* Pbar;            // adjoint: [nb][N+1][N+2][4] cotangents of the panels
   double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
   const double2* tw;        // [M] exp(-2 pi i k / M)
   const int64_t* off;       // [nb] complex-slot offset of each member in a state
@@ -77,9 +80,12 @@ struct SynthInput {
   double coef[kMaxSources];
   int nsrc;
   double coriolis;  // 2 Omega sqrt(4 pi / 3): absolute-vorticity fold of zeta[1,0]
+  const double2* adj;  // SYNTH_ADJ: cotangent n_bar of the nonlinear term (state array)
 };
 
-enum SynthMode { SYNTH_NONLINEAR = 0, SYNTH_GRID = 1 };
+// SYNTH_ADJ: the four forward fields plus a fifth, lambda^(-1/2) n_bar (the
+// adjoint of the analysis), written to GroupView::Fa.
+enum SynthMode { SYNTH_NONLINEAR = 0, SYNTH_GRID = 1, SYNTH_ADJ = 2 };
 enum AnalMode { ANAL_NONLINEAR = 0, ANAL_STEP_ITER = 1, ANAL_STEP_FINAL = 2 };
 
 struct AnalOutput {
@@ -103,6 +109,14 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s);
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s);
+hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s);
+hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s);
+hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream_t s);
+hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, double2* hist_bar,
+                                   double2* nbar, hipStream_t s);
+hipError_t launch_step_adjoint_post(const GroupView& g, const SynthInput& pred,
+                                    int64_t state_count, double2* hist_bar, const double2* abar,
+                                    hipStream_t s);
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
                                hipStream_t s);
 hipError_t launch_analysis_lp(const GroupView& g, const AnalOutput& out, int prec, hipStream_t s);
@@ -121,9 +135,10 @@ template <>
 __host__ __device__ inline const float* analysis_table<float>(const GroupView& g) { return g.T2f; }
 
 // Dynamic LDS of the launches (validated against 64 KiB at init).
-size_t synthesis_lds_bytes(int N);
+size_t synthesis_lds_bytes(int N, int NF);
 size_t ring_lds_bytes(int M);
 size_t analysis_lds_bytes(int nh);
+size_t synthesis_adjoint_lds_bytes(int nh);
 size_t synthesis_lp_lds_bytes(int N);
 size_t analysis_lp_lds_bytes(int nh);
 

@@ -208,6 +208,22 @@ __device__ void load_pair(double2* x, const double2* __restrict__ Fa,
   for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
 }
 
+// Spectrum of one real field, G[m] (read from F[f][m][lat]) for m >= 1 scaled
+// by s1: x_0 = Re G_0, x_m = s1 G_m, x_{M-m} = s1 conj(G_m), zero elsewhere.
+__device__ void load_single(double2* x, const double2* __restrict__ G, double s1, int lat, int N,
+                            int M, int nlat) {
+  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
+    const double2 v = G[(int64_t)m * nlat + lat];
+    if (m == 0) {
+      x[0] = make_double2(v.x, 0.0);
+    } else {
+      x[pad(m)] = make_double2(s1 * v.x, s1 * v.y);
+      x[pad(M - m)] = make_double2(s1 * v.x, -s1 * v.y);
+    }
+  }
+  for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
+}
+
 }  // namespace
 
 size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(M) + M / 2); }
@@ -287,6 +303,108 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     const double2 X = A0[pad(m)];
     Wl[m] = make_double2(c * X.x, c * X.y);
   }
+}
+
+// Adjoint of the ring kernel (vector-Jacobian product on the real grid
+// values): given the cotangent of the ring spectra Q (the fifth field of Fa,
+// produced by the adjoint of the analysis), recompute the four forward grid
+// fields of the ring, form
+//   qbar_j = c_lat Re(Qbar_0 + sum_{m>=1} Qbar_m e^{i m phi_j})   (weighted r2c)^T
+//   gbar0 = qbar g2 / s^2, gbar2 = qbar g0 / s^2, gbar1 = -qbar g3 / s^2, gbar3 = -qbar g1 / s^2
+// and the cotangents of the field spectra (the c2r of the synthesis)^T:
+//   Gbar_0 = sum_j gbar_j,  Gbar_m = 2 sum_j gbar_j e^{-i m phi_j}  (m >= 1),
+// written to Fbar[b][f][lat][m]. c_lat = (2 pi / M) w_p.
+template <int MAXM, int NT>
+__global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
+  constexpr int PTS = (MAXM + NT - 1) / NT;
+  const int N = g.N, M = g.M, nlat = g.nlat;
+  const int lat = blockIdx.x;
+  const int b = blockIdx.y;
+  const int p = lat < g.nh ? lat : nlat - 1 - lat;
+  const int PL = padded_len(M);
+  extern __shared__ double2 lds[];
+  double2* A0 = lds;
+  double2* A1 = lds + PL;
+  double2* tw = lds + 2 * PL;
+  for (int j = threadIdx.x; j < M / 2; j += blockDim.x) tw[j] = g.tw[j];
+  const double x = g.mu[p];
+  const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* F5 = g.Fa + (int64_t)b * 5 * fstride;
+
+  // forward grid fields of this ring
+  load_pair(A0, F5, F5 + 2 * fstride, lat, N, M, nlat);
+  load_pair(A1, F5 + fstride, F5 + 3 * fstride, lat, N, M, nlat);
+  __syncthreads();
+  fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+  double g0[PTS], g1[PTS], g2[PTS], g3[PTS];
+#pragma unroll
+  for (int c = 0; c < PTS; ++c) {
+    const int j = threadIdx.x + c * NT;
+    g0[c] = g1[c] = g2[c] = g3[c] = 0.0;
+    if (j < M) {
+      const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
+      g0[c] = z02.x;
+      g2[c] = z02.y;
+      g1[c] = z13.x;
+      g3[c] = z13.y;
+    }
+  }
+  __syncthreads();
+  // cotangent of the grid product
+  load_single(A0, F5 + 4 * fstride, 0.5, lat, N, M, nlat);
+  __syncthreads();
+  fft<1, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+  const double clat = (6.283185307179586477 / M) * g.w[p];
+  double qb[PTS];
+#pragma unroll
+  for (int c = 0; c < PTS; ++c) {
+    const int j = threadIdx.x + c * NT;
+    qb[c] = (j < M) ? clat * A0[pad(j)].x * inv_sin2 : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < PTS; ++c) {
+    const int j = threadIdx.x + c * NT;
+    if (j < M) {
+      A0[pad(j)] = make_double2(qb[c] * g2[c], qb[c] * g0[c]);     // gbar0 + i gbar2
+      A1[pad(j)] = make_double2(-qb[c] * g3[c], -qb[c] * g1[c]);   // gbar1 + i gbar3
+    }
+  }
+  __syncthreads();
+  fft<2, MAXM, NT>(A0, A1, plan, M, tw, -1.0);
+  // unpack two real transforms per array: z = a + i b ->
+  // A_m = (Z_m + conj Z_{M-m}) / 2, B_m = (Z_m - conj Z_{M-m}) / (2 i); times 2 for m >= 1
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
+    const double sc = (m == 0) ? 0.5 : 1.0;
+#pragma unroll
+    for (int arr = 0; arr < 2; ++arr) {
+      const double2* X = arr ? A1 : A0;
+      const double2 zm = X[pad(m)];
+      const double2 zc = X[pad((M - m) % M)];
+      const double2 ga = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
+      const double2 gb = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
+      Fb[(int64_t)(arr ? 1 : 0) * fstride + m] = ga;
+      Fb[(int64_t)(arr ? 3 : 2) * fstride + m] = gb;
+    }
+  }
+}
+
+hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
+  dim3 grid(g.nlat, g.nb);
+  const size_t lds = ring_lds_bytes(g.M);
+  if (g.M <= 256)
+    hipLaunchKernelGGL((k_ring_adj<256, 128>), grid, dim3(128), lds, s, g, plan);
+  else if (g.M <= 512)
+    hipLaunchKernelGGL((k_ring_adj<512, 256>), grid, dim3(256), lds, s, g, plan);
+  else if (g.M <= 768)
+    hipLaunchKernelGGL((k_ring_adj<768, 256>), grid, dim3(256), lds, s, g, plan);
+  else if (g.M <= 1024)
+    hipLaunchKernelGGL((k_ring_adj<1024, 512>), grid, dim3(512), lds, s, g, plan);
+  else
+    hipLaunchKernelGGL((k_ring_adj<kMaxM, 512>), grid, dim3(512), lds, s, g, plan);
+  return hipGetLastError();
 }
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,

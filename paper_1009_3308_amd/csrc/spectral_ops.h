@@ -52,15 +52,15 @@ __device__ inline double2 panel_value(const double2* a, int N, int m, int k, int
     const double lam = (double)ll * (ll + 1);
     const double r = zeta ? sqrt(lam) : 1.0 / sqrt(lam);
     double2 z = make_double2(a[kk].x * r, a[kk].y * r);
-    if (zeta && mode == SYNTH_NONLINEAR && m == 0 && ll == 1) z.x += coriolis;
+    if (zeta && mode != SYNTH_GRID && m == 0 && ll == 1) z.x += coriolis;
     return z;
   };
-  if (f == 0 || (f == 3 && mode == SYNTH_NONLINEAR)) {
+  if (f == 0 || (f == 3 && mode != SYNTH_GRID)) {
     const double2 c = coef(k, f == 3);
     return make_double2(-dm * c.y, dm * c.x);  // i m c
   }
   if (f == 3) return make_double2(0.0, 0.0);
-  if (f == 2 && mode != SYNTH_NONLINEAR) return coef(k, true);
+  if (f == 2 && mode == SYNTH_GRID) return coef(k, true);
   const bool zeta = (f == 2);
   const double e_l = (l > m) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
   const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
@@ -69,8 +69,9 @@ __device__ inline double2 panel_value(const double2* a, int N, int m, int k, int
   return make_double2(cm * lo.x - cp * hi.x, cm * lo.y - cp * hi.y);
 }
 
-// All four panels of order m into pan[4k + f], k < L (one degree per thread,
+// All four panels of order m into pan[NF k + f], k < L (one degree per thread,
 // the neighbouring coefficients shared by the four fields).
+template <int NF = 4>
 __device__ inline void build_panel(double2* pan, const double2* a, int N, int m, int L, int mode,
                                    double coriolis) {
   const double dm = (double)m;
@@ -87,20 +88,20 @@ __device__ inline void build_panel(double2* pan, const double2* a, int N, int m,
         const double sq = sqrt(lam), r = 1.0 / sq;
         ps[d] = make_double2(a[kk].x * r, a[kk].y * r);
         zs[d] = make_double2(a[kk].x * sq, a[kk].y * sq);
-        if (mode == SYNTH_NONLINEAR && m == 0 && ll == 1) zs[d].x += coriolis;
+        if (mode != SYNTH_GRID && m == 0 && ll == 1) zs[d].x += coriolis;
       }
     }
     const double e_l = (l > m) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
     const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
     const double cm = (dl - 1.0) * e_l, cp = (dl + 2.0) * e_l1;
-    pan[4 * k + 0] = make_double2(-dm * ps[1].y, dm * ps[1].x);
-    pan[4 * k + 1] = make_double2(cm * ps[0].x - cp * ps[2].x, cm * ps[0].y - cp * ps[2].y);
-    if (mode == SYNTH_NONLINEAR) {
-      pan[4 * k + 2] = make_double2(cm * zs[0].x - cp * zs[2].x, cm * zs[0].y - cp * zs[2].y);
-      pan[4 * k + 3] = make_double2(-dm * zs[1].y, dm * zs[1].x);
+    pan[NF * k + 0] = make_double2(-dm * ps[1].y, dm * ps[1].x);
+    pan[NF * k + 1] = make_double2(cm * ps[0].x - cp * ps[2].x, cm * ps[0].y - cp * ps[2].y);
+    if (mode != SYNTH_GRID) {
+      pan[NF * k + 2] = make_double2(cm * zs[0].x - cp * zs[2].x, cm * zs[0].y - cp * zs[2].y);
+      pan[NF * k + 3] = make_double2(-dm * zs[1].y, dm * zs[1].x);
     } else {
-      pan[4 * k + 2] = zs[1];
-      pan[4 * k + 3] = make_double2(0.0, 0.0);
+      pan[NF * k + 2] = zs[1];
+      pan[NF * k + 3] = make_double2(0.0, 0.0);
     }
   }
 }

@@ -407,3 +407,36 @@ def test_oracle_gradient_vs_central_differences():
             fd = (loss_of(x + eps * d) - loss_of(x - eps * d)) / (2 * eps)
         ad = float((g * d).sum())
         assert abs(fd - ad) < 1e-7 * max(1.0, abs(ad))
+
+
+def test_oracle_vjp_dot_product_exact():
+    """n and one step are quadratic in the state, so the central difference
+    (F(a + d) - F(a - d)) / 2 equals J d up to rounding, for any size of d:
+    <J d, c> must equal <d, J^T c> from autograd to rounding."""
+    N = 9
+    S = O.Sphere(N)
+    a = O.to_tensor(I.initial_state(N))
+    d = O.to_tensor(I.directions(N, 1)[0])
+    c = O.to_tensor(I.cotangent(N))
+    x = a.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad((c.conj() * S.nonlinear(x, OMEGA)).real.sum(), x)
+    with torch.no_grad():
+        jd = (S.nonlinear(a + d, OMEGA) - S.nonlinear(a - d, OMEGA)) / 2
+    lhs, rhs = float((jd.conj() * c).real.sum()), float((d.conj() * g).real.sum())
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+    st = O.Stepper(S, 1e-3, OMEGA, 1e-2, order=3)
+    f = O.to_tensor(I.forcing(N))
+    hist = [O.to_tensor(I.member_state(j, N)) for j in range(4)]
+    dh = [O.to_tensor(I.directions(N, 5)[j + 1]) for j in range(4)]
+    ch = [O.to_tensor(I.cotangent(N, j)) for j in range(4)]
+    xs = [h.clone().requires_grad_(True) for h in hist]
+    new = st.step(xs, f, 4)
+    gs = torch.autograd.grad(sum((cj.conj() * y).real.sum() for cj, y in zip(ch, new)), xs,
+                             allow_unused=True)
+    with torch.no_grad():
+        up = st.step([h + e for h, e in zip(hist, dh)], f, 4)
+        dn = st.step([h - e for h, e in zip(hist, dh)], f, 4)
+    lhs = sum(float(((u - v) / 2).conj().mul(cj).real.sum()) for u, v, cj in zip(up, dn, ch))
+    rhs = sum(float((e.conj() * gj).real.sum()) for e, gj in zip(dh, gs) if gj is not None)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
