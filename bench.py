@@ -27,11 +27,21 @@ if ROOT not in sys.path:
 
 METRIC = "NSE steps/sec at T255 & T511: FP64 vs split-BF16 (err vs FP64); adjoint/fwd time"
 HBM_PEAK_GBS = 8000.0
+# each kernel launch of the instrumented pass is issued this many times between
+# its two HIP events, which spreads the event overhead (about 2.5 us) thin
+PROFILE_REPEAT = 10
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# sources each kernel is built from: measured traffic is used only while these
+# are unchanged since the counters were taken
 KERNEL_SOURCES = {
-    "synthesis": "paper_1009_3308_amd/csrc/synthesis.hip",
-    "ring": "paper_1009_3308_amd/csrc/ring_fft.hip",
-    "analysis": "paper_1009_3308_amd/csrc/analysis.hip",
+    "synthesis": ["paper_1009_3308_amd/csrc/synthesis.hip",
+                  "paper_1009_3308_amd/csrc/spectral_ops.h",
+                  "paper_1009_3308_amd/csrc/nse_internal.h"],
+    "ring": ["paper_1009_3308_amd/csrc/ring_fft.hip",
+             "paper_1009_3308_amd/csrc/nse_internal.h"],
+    "analysis": ["paper_1009_3308_amd/csrc/analysis.hip",
+                 "paper_1009_3308_amd/csrc/spectral_ops.h",
+                 "paper_1009_3308_amd/csrc/nse_internal.h"],
 }
 
 
@@ -59,8 +69,11 @@ def algorithmic_bytes(N, nlat, order, nsrc):
 
 
 def source_sha(kernel):
-    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, workload):
@@ -137,6 +150,42 @@ def precision_errors(pkg, torch, N, nu, steps):
     return out
 
 
+def adjoint_timing(pkg, torch, N, nu, steps, every=20, reps=3):
+    """Forward time of `steps` graph-replayed steps and backward time (segment
+    recompute from checkpoints every `every` steps plus the step adjoints) of
+    the misfit gradient 0.5 sum |alpha(T) - alpha_target|^2 with respect to
+    alpha(0); the median of `reps` runs after one warm-up run."""
+    import statistics
+
+    import nse_inputs as I
+    from paper_1009_3308_amd.adjoint import trajectory
+    stream = torch.cuda.Stream()
+    fw, bw = [], []
+    with torch.cuda.stream(stream):
+        s = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, graph=True, stream=stream)
+        f, tg = pkg.to_device(I.forcing(N)), pkg.to_device(I.target_state(N))
+        w = torch.where(torch.as_tensor(I.degrees_orders(N)[1], device="cuda") > 0, 2.0, 1.0)
+        for r in range(reps + 1):
+            a = pkg.to_device(I.initial_state(N)).requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = trajectory(s, a, f, steps, checkpoint_every=every)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            d = out - tg
+            loss = 0.5 * (w * (d.real ** 2 + d.imag ** 2)).sum()
+            (g,) = torch.autograd.grad(loss, a)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if r > 0:
+                fw.append(t1 - t0)
+                bw.append(t2 - t1)
+        s.close()
+    fwd, bwd = statistics.median(fw), statistics.median(bw)
+    return {"fwd_ms": round(1e3 * fwd, 3), "bwd_ms": round(1e3 * bwd, 3),
+            "ratio": round(bwd / fwd, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +196,7 @@ def main():
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-t511", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB read + 256 MiB write kernel, the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -191,7 +241,7 @@ def main():
     # per-kernel durations: instrumented eager pass of the same steps
     nlat = sph.nlat[0]
     with torch.cuda.stream(stream):
-        sph.profile(True)
+        sph.profile(True, repeat=PROFILE_REPEAT)
         run_steps(sph, hist, f, args.warmup + args.steps, args.profile_steps)
         prof = sph.profile_read()
         sph.profile(False)
@@ -236,6 +286,13 @@ def main():
                     extra[f"t511_{prec}_steps_per_s"] / extra["t511_fp64_steps_per_s"], 3)
         log("bench: T511 precision errors (200 steps)")
         extra.update({f"t511_{k}": v for k, v in precision_errors(pkg, torch, 511, 1e-5, 200).items()})
+
+    if not args.no_adjoint:
+        log("bench: T255 adjoint, 200 steps, checkpoints every 20")
+        adj = adjoint_timing(pkg, torch, N, nu, 200)
+        extra["t255_adjoint_200_steps"] = adj
+        extra["t255_adjoint_over_forward"] = adj["ratio"]
+        log(f"bench: adjoint {adj}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -161,6 +161,16 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist,
  * phi_j = 2 pi j / M). */
 nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out);
 
+/* Discrete projection of a grid velocity field onto the divergence-free
+ * basis, alpha[l,m] = (u, Z[l,m])_M (Section 3, the discrete vector inner
+ * product and the orthogonal projection L_N; the initial state of the ODE is
+ * obtained this way from u_0). u_grid: device array [member][2][nlat][M] of
+ * doubles holding u_theta then u_phi on the grid of nse_synthesize;
+ * alpha_out: device state array, overwritten (l = 0 slot and Im of m = 0
+ * written as 0). For u in the span of Z[l,m], l <= N, this inverts
+ * nse_synthesize exactly (up to rounding). */
+nse_status nse_analyze_velocity(nse_ctx* ctx, const double* u_grid, double* alpha_out);
+
 /* Normalised Legendre values of one member's table: writes Pbar[l,m](mu_p)
  * for l = m..N+1 and the nlat/2 northern nodes p as a device array
  * [l-m][p] of doubles. For testing the FP64 table. */
@@ -175,11 +185,17 @@ enum {
   NSE_KERNEL_KINDS = 3
 };
 
-/* Per-kernel timing. While enabled, every kernel launch of the context is
- * bracketed by HIP events on the context stream and nse_step does not replay
- * graphs. nse_profile_read waits for the stream and returns, for kernel kind
- * `kind`, the launches and their summed duration in milliseconds since the
- * last read or enable; it then resets that kind's counters. */
+/* Per-kernel timing. enable = R > 0 turns it on: every kernel launch of the
+ * context is then issued R times back to back between two HIP events on the
+ * context stream (the event overhead is spread over the R launches), and
+ * nse_step does not replay graphs. The launches are repeated on identical
+ * inputs; a step's final analysis, which rotates the history in place, is
+ * repeated from a saved copy of the history and redone once after the
+ * events, so results are unchanged. enable = 0 turns timing off; R is at
+ * most 1000. nse_profile_read waits for the stream and returns, for kernel
+ * kind `kind`, the logical launches and their summed per-launch duration
+ * (bracket time / R) in milliseconds since the last read or enable; it then
+ * resets that kind's counters. */
 nse_status nse_profile_enable(nse_ctx* ctx, int32_t enable);
 nse_status nse_profile_read(nse_ctx* ctx, int32_t kind, int64_t* launches,
                             double* total_ms);

@@ -110,6 +110,12 @@ def cotangent(N: int, index: int = 0) -> np.ndarray:
     return out
 
 
+def grid_noise(seed: int, nlat: int, M: int, fields: int = 2) -> np.ndarray:
+    """Seeded N(0,1) grid values [fields][nlat][M] (a field with every scale,
+    not divergence-free), for projection tests."""
+    return np.random.default_rng(seed).standard_normal((fields, nlat, M))
+
+
 def ensemble_viscosities(count: int, lo: float = 1e-5, hi: float = 1e-3) -> np.ndarray:
     """nu_i log-uniform in [lo, hi]."""
     rng = np.random.default_rng(SEED_ENSEMBLE_NU)

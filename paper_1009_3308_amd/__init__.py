@@ -36,6 +36,7 @@ EXPORTS = (
     "nse_state_count", "nse_member_grid", "nse_nonlinear", "nse_step",
     "nse_nonlinear_adjoint", "nse_step_adjoint", "nse_synthesize", "nse_legendre_values",
     "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
+    "nse_analyze_velocity",
 )
 
 KERNEL_KINDS = {"synthesis": 0, "ring": 1, "analysis": 2}
@@ -84,6 +85,7 @@ def lib():
         "nse_nonlinear_adjoint": (st, [vp, dp, dp, dp]),
         "nse_step_adjoint": (st, [vp, dp, dp, i64, dp]),
         "nse_synthesize": (st, [vp, dp, dp]),
+        "nse_analyze_velocity": (st, [vp, dp, dp]),
         "nse_legendre_values": (st, [vp, i32, i32, dp]),
         "nse_sync": (st, [vp]),
         "nse_profile_enable": (st, [vp, i32]),
@@ -246,6 +248,24 @@ class Sphere:
             o += s
         return res
 
+    def analyze_velocity(self, grids, out=None):
+        """alpha = (u, Z)_M from per-member grids [>=2, nlat, M] (u_theta, u_phi first)."""
+        import torch
+        if len(grids) != len(self.member_specs):
+            raise ValueError("need one grid per member")
+        parts = []
+        for g, nl in zip(grids, self.nlat):
+            if g.dim() != 3 or g.shape[0] < 2 or tuple(g.shape[1:]) != (nl, 2 * nl):
+                raise ValueError(f"member grid must be [>=2, {nl}, {2 * nl}]")
+            parts.append(g[:2].reshape(-1))
+        flat = torch.cat(parts).to(torch.float64).contiguous()
+        if out is None:
+            out = self.new_state()
+        _check(lib().nse_analyze_velocity(self._handle(), _ptr(flat, torch.float64),
+                                          _ptr(out, torch.complex128, self.state_count,
+                                               "alpha_out")), self._h)
+        return out
+
     def legendre_values(self, member: int, m: int):
         """Pbar[l,m](mu_p), l = m..N+1, northern nodes: float64 tensor [N+2-m, ceil(nlat/2)]."""
         import torch
@@ -256,9 +276,10 @@ class Sphere:
                self._h)
         return out.view(N + 2 - m, nh)
 
-    def profile(self, enable: bool = True):
-        """Starts (or stops) per-kernel event timing on the context stream."""
-        _check(lib().nse_profile_enable(self._handle(), 1 if enable else 0), self._h)
+    def profile(self, enable: bool = True, repeat: int = 1):
+        """Starts (or stops) per-kernel event timing on the context stream; each
+        launch is issued `repeat` times between its events (same results)."""
+        _check(lib().nse_profile_enable(self._handle(), int(repeat) if enable else 0), self._h)
 
     def profile_read(self):
         """{kernel: (launches, total_ms)} since the last read; resets the counters."""

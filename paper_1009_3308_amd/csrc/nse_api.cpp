@@ -69,6 +69,11 @@ struct Group {
     g.nb = 1;
     g.F = d_F + (int64_t)i * 4 * nlat * (N + 1);
     g.W = d_W + (int64_t)i * nlat * (N + 1);
+    if (d_Fa) {
+      g.Fa = d_Fa + (int64_t)i * 5 * nlat * (N + 1);
+      g.Fbar = d_Fbar + (int64_t)i * 4 * nlat * (N + 1);
+      g.Pbar = d_Pbar + (int64_t)i * (N + 1) * (N + 2) * 4;
+    }
     g.off = d_off + i;
     g.nu = d_nu + i;
     return g;
@@ -96,10 +101,14 @@ struct nse_ctx {
   std::string err;
   // captured step chunks keyed by (hist, forcing, chunk length)
   std::map<std::tuple<const void*, const void*, int>, GraphEntry> graphs;
-  // per-kernel timing
+  // per-kernel timing: every launch is issued `profile_repeat` times between
+  // one pair of events (0 = timing off)
   bool profiling = false;
+  int profile_repeat = 0;
+  double2* d_hist_save = nullptr;  // history copy for repeated in-place step updates
   struct Pending {
     int kind;
+    int repeat;
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
@@ -265,7 +274,7 @@ nse_status collect_profile(nse_ctx* c) {
     float ms = 0.f;
     NSE_HIP(c, hipEventElapsedTime(&ms, p.a, p.b));
     c->prof_count[p.kind] += 1;
-    c->prof_ms[p.kind] += ms;
+    c->prof_ms[p.kind] += ms / p.repeat;
     c->event_pool.push_back(p.a);
     c->event_pool.push_back(p.b);
   }
@@ -273,18 +282,21 @@ nse_status collect_profile(nse_ctx* c) {
   return NSE_OK;
 }
 
-// Runs one launcher, bracketed by events when profiling.
+// Runs one launcher. When profiling, the launch is issued profile_repeat
+// times back to back between two events, so that the event overhead is
+// spread over the repeats (the launchers passed here are pure functions of
+// their inputs, or are made so by the caller).
 template <typename F>
 nse_status timed_launch(nse_ctx* c, int kind, F&& launch) {
   if (!c->profiling) {
     NSE_HIP(c, launch());
     return NSE_OK;
   }
-  nse_ctx::Pending p{kind, nullptr, nullptr};
+  nse_ctx::Pending p{kind, c->profile_repeat, nullptr, nullptr};
   NSE_HIP(c, take_event(c, &p.a));
   NSE_HIP(c, take_event(c, &p.b));
   NSE_HIP(c, hipEventRecord(p.a, c->stream));
-  NSE_HIP(c, launch());
+  for (int r = 0; r < p.repeat; ++r) NSE_HIP(c, launch());
   NSE_HIP(c, hipEventRecord(p.b, c->stream));
   c->pending.push_back(p);
   if (c->pending.size() > 4096) return collect_profile(c);
@@ -314,8 +326,23 @@ nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out
     s = timed_launch(c, NSE_KERNEL_RING,
                      [&] { return launch_ring(v, g.plan, SYNTH_NONLINEAR, nullptr, c->stream); });
     if (s != NSE_OK) return s;
+    // the final sweep of a step rotates the history in place: repeated timing
+    // launches run from a saved copy, which is restored for one last launch
+    const bool rotates = out.mode == ANAL_STEP_FINAL && c->profiling && c->profile_repeat > 1;
+    const size_t hbytes = sizeof(double2) * (size_t)out.depth * c->state_count;
+    if (rotates) {
+      if (!c->d_hist_save)
+        NSE_HIP(c, dalloc(&c->d_hist_save, (size_t)(c->params.order + 1) * c->state_count));
+      NSE_HIP(c, hipMemcpyAsync(c->d_hist_save, out.hist, hbytes, hipMemcpyDeviceToDevice,
+                                c->stream));
+    }
     s = timed_launch(c, NSE_KERNEL_ANALYSIS, [&] { return launch_anal_any(v, out, c->stream); });
     if (s != NSE_OK) return s;
+    if (rotates) {
+      NSE_HIP(c, hipMemcpyAsync(out.hist, c->d_hist_save, hbytes, hipMemcpyDeviceToDevice,
+                                c->stream));
+      NSE_HIP(c, launch_anal_any(v, out, c->stream));
+    }
   }
   return NSE_OK;
 }
@@ -549,6 +576,7 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_flag);
   (void)hipFree(ctx->d_nbar);
   (void)hipFree(ctx->d_abar);
+  (void)hipFree(ctx->d_hist_save);
   delete ctx;
   return NSE_OK;
 }
@@ -713,6 +741,23 @@ nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out) {
   return NSE_OK;
 }
 
+nse_status nse_analyze_velocity(nse_ctx* ctx, const double* u_grid, double* alpha_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!u_grid || !alpha_out) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  nse_status s = ensure_adjoint_buffers(ctx);
+  if (s != NSE_OK) return s;
+  int64_t goff = 0;
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_ring_project(v, g.plan, u_grid + goff, ctx->stream));
+    NSE_HIP(ctx, launch_synthesis_adjoint(v, ctx->stream));
+    NSE_HIP(ctx, launch_prep_adjoint(v, (double2*)alpha_out, ctx->stream));
+    goff += (int64_t)2 * g.nlat * g.M;
+  }
+  return NSE_OK;
+}
+
 nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m, double* out) {
   if (!ctx) return NSE_ERR_ARG;
   if (!out) return fail(ctx, NSE_ERR_ARG, "out is NULL");
@@ -734,7 +779,10 @@ nse_status nse_profile_enable(nse_ctx* ctx, int32_t enable) {
     ctx->prof_count[k] = 0;
     ctx->prof_ms[k] = 0.0;
   }
+  if (enable < 0 || enable > 1000)
+    return fail(ctx, NSE_ERR_ARG, "profile repeat count %d outside 0..1000", enable);
   ctx->profiling = enable != 0;
+  ctx->profile_repeat = enable;
   return NSE_OK;
 }
 

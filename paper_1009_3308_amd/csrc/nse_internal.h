@@ -110,6 +110,8 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
                        hipStream_t s);
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s);
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s);
+hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const double* u_grid,
+                               hipStream_t s);
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s);
 hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream_t s);
 hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, double2* hist_bar,

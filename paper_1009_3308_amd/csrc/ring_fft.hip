@@ -391,6 +391,46 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   }
 }
 
+// Longitude part of the projection (u, Z[l,m])_M of a grid velocity field:
+// per ring, the real transforms Ut_m = sum_j u_theta e^{-i m phi_j} and
+// Up_m = sum_j u_phi e^{-i m phi_j} (one complex FFT of u_theta + i u_phi),
+// scaled by c = (2 pi / M) w_p / sin(theta_p) and written to
+// Fbar[b][f][lat][m] as (c Ut, -c Up, 0, 0). The latitude sums and the degree
+// coupling of d/dtheta are done by the unweighted analysis and the prologue
+// transpose, since conj(Z[l,m]) = lambda^(-1/2) (-i m Pbar / sin, -dPbar/dtheta) e^{-i m phi}
+// and sin(theta) dPbar/dtheta couples degrees l - 1 and l + 1.
+template <int MAXM, int NT>
+__global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
+                                                     const double* __restrict__ u_grid) {
+  const int N = g.N, M = g.M, nlat = g.nlat;
+  const int lat = blockIdx.x;
+  const int b = blockIdx.y;
+  const int p = lat < g.nh ? lat : nlat - 1 - lat;
+  const int PL = padded_len(M);
+  extern __shared__ double2 lds[];
+  double2* A0 = lds;
+  double2* tw = lds + 2 * PL;
+  for (int j = threadIdx.x; j < M / 2; j += blockDim.x) tw[j] = g.tw[j];
+  const double* ut = u_grid + ((int64_t)(2 * b) * nlat + lat) * M;
+  const double* up = ut + (int64_t)nlat * M;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) A0[pad(j)] = make_double2(ut[j], up[j]);
+  __syncthreads();
+  fft<1, MAXM, NT>(A0, A0, plan, M, tw, -1.0);
+  const double x = g.mu[p];
+  const double c = (6.283185307179586477 / M) * g.w[p] / sqrt((1.0 - x) * (1.0 + x));
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
+    const double2 zm = A0[pad(m)];
+    const double2 zc = A0[pad((M - m) % M)];
+    const double h = 0.5 * c;
+    Fb[m] = make_double2(h * (zm.x + zc.x), h * (zm.y - zc.y));
+    Fb[fstride + m] = make_double2(-h * (zm.y + zc.y), h * (zm.x - zc.x));
+    Fb[2 * fstride + m] = make_double2(0.0, 0.0);
+    Fb[3 * fstride + m] = make_double2(0.0, 0.0);
+  }
+}
+
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
   dim3 grid(g.nlat, g.nb);
   const size_t lds = ring_lds_bytes(g.M);
@@ -404,6 +444,23 @@ hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStrea
     hipLaunchKernelGGL((k_ring_adj<1024, 512>), grid, dim3(512), lds, s, g, plan);
   else
     hipLaunchKernelGGL((k_ring_adj<kMaxM, 512>), grid, dim3(512), lds, s, g, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const double* u_grid,
+                               hipStream_t s) {
+  dim3 grid(g.nlat, g.nb);
+  const size_t lds = ring_lds_bytes(g.M);
+  if (g.M <= 256)
+    hipLaunchKernelGGL((k_ring_project<256, 128>), grid, dim3(128), lds, s, g, plan, u_grid);
+  else if (g.M <= 512)
+    hipLaunchKernelGGL((k_ring_project<512, 256>), grid, dim3(256), lds, s, g, plan, u_grid);
+  else if (g.M <= 768)
+    hipLaunchKernelGGL((k_ring_project<768, 256>), grid, dim3(256), lds, s, g, plan, u_grid);
+  else if (g.M <= 1024)
+    hipLaunchKernelGGL((k_ring_project<1024, 512>), grid, dim3(512), lds, s, g, plan, u_grid);
+  else
+    hipLaunchKernelGGL((k_ring_project<kMaxM, 512>), grid, dim3(512), lds, s, g, plan, u_grid);
   return hipGetLastError();
 }
 

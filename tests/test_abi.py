@@ -91,6 +91,7 @@ def test_null_arguments(L):
                              ctypes.byref(ctypes.c_void_p())) == pkg.NSE_ERR_ARG
     for fn, args in [("nse_nonlinear", (None, None, None)), ("nse_step", (None, None, None, 0, 1)),
                      ("nse_sync", (None,)), ("nse_synthesize", (None, None, None)),
+                     ("nse_analyze_velocity", (None, None, None)),
                      ("nse_nonlinear_adjoint", (None, None, None, None)),
                      ("nse_step_adjoint", (None, None, None, 0, None))]:
         assert getattr(L, fn)(*args) == pkg.NSE_ERR_ARG

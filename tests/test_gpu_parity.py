@@ -302,3 +302,29 @@ def test_argument_errors_through_binding():
     with pytest.raises(ValueError):
         s.nonlinear(torch.zeros(5, dtype=torch.complex128, device="cuda"))
     s.close()
+
+
+@pytest.mark.parametrize("iters", [1, 2])
+def test_profiled_steps_equal_plain_steps_bitwise(iters):
+    """Timing mode repeats every launch between its events; the history after
+    profiled steps must be bitwise that of plain steps."""
+    N = 63
+    _say(f"case: profiled steps N={N} newton_iters={iters}")
+    a, f = pkg.to_device(I.initial_state(N)), pkg.to_device(I.forcing(N))
+    out = []
+    for repeat in (0, 5):
+        s = pkg.Sphere([(N, 0, 1e-4)], omega=OMEGA, dt=1e-3, newton_iters=iters)
+        h = s.new_history()
+        h[0] = a
+        if repeat:
+            s.profile(True, repeat=repeat)
+        s.step(h, f, 0, 12)
+        if repeat:
+            prof = s.profile_read()
+            assert prof["synthesis"][0] == 12 * iters and prof["analysis"][0] == 12 * iters
+            assert all(ms > 0 for _, ms in prof.values())
+            s.profile(False)
+        s.sync()
+        out.append(h.clone())
+        s.close()
+    assert torch.equal(out[0], out[1])
