@@ -186,6 +186,59 @@ def adjoint_timing(pkg, torch, N, nu, steps, every=20, reps=3):
             "ratio": round(bwd / fwd, 3)}
 
 
+def ensemble_timing(pkg, torch, steps=100, warmup=10):
+    """Mixed-truncation ensemble (24 x N=63, 24 x N=127, 16 x N=255; nu log-uniform in
+    [1e-5, 1e-3]; Omega = 2 pi, dt = 1e-3, NDF2): member-steps/s of one context that steps
+    all members (one graph per 10-step chunk holding every group's kernels), and of the same
+    members stepped one context per member (per-member launches), both after `warmup` steps."""
+    import nse_inputs as I
+    Ns = I.ensemble_truncations()
+    nus = I.ensemble_viscosities(len(Ns))
+    specs = [(N, 0, float(nu)) for N, nu in zip(Ns, nus)]
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        s = pkg.Sphere(specs, omega=2 * math.pi, dt=1e-3, graph=True, stream=stream)
+        h, f = s.new_history(), s.new_state()
+        for i, (N, _, _) in enumerate(specs):
+            h[0, s.member_slice(i)] = pkg.to_device(I.member_state(i, N))
+            f[s.member_slice(i)] = pkg.to_device(I.forcing(N))
+        s.step(h, f, 0, warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(h, f, warmup, steps)
+        s.sync()
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        finite = bool(torch.isfinite(torch.view_as_real(h)).all())
+        s.close()
+        ctxs = []
+        for i, spec in enumerate(specs):
+            c = pkg.Sphere([spec], omega=2 * math.pi, dt=1e-3, graph=True, stream=stream)
+            hc = c.new_history()
+            hc[0] = pkg.to_device(I.member_state(i, spec[0]))
+            fc = pkg.to_device(I.forcing(spec[0]))
+            c.step(hc, fc, 0, warmup)
+            ctxs.append((c, hc, fc))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, hc, fc in ctxs:
+            c.step(hc, fc, warmup, steps)
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        for c, _, _ in ctxs:
+            c.close()
+    n = len(specs)
+    out["members"] = n
+    out["member_steps_per_s"] = round(n * steps / t_one, 1)
+    out["ms_per_step"] = round(1e3 * t_one / steps, 4)
+    out["per_member_contexts_member_steps_per_s"] = round(n * steps / t_sep, 1)
+    out["speedup_vs_per_member"] = round(t_sep / t_one, 3)
+    out["finite"] = finite
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)

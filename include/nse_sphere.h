@@ -68,6 +68,8 @@ enum {
 
 enum {
   NSE_FLAG_GRAPH = 1,       /* replay nse_step through a captured hipGraph      */
+  NSE_FLAG_AUTOTUNE = 2,    /* time the member-block sizes of every FP64 group
+                               with >= 2 members at init and keep the fastest */
   NSE_FLAG_CHECK_FINITE = 4 /* flag NaN/Inf in the state; nse_sync reports it   */
 };
 
@@ -106,6 +108,22 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members,
 
 /* Waits for the context's stream, frees everything it owns. NULL is a no-op. */
 nse_status nse_sphere_destroy(nse_ctx* ctx);
+
+/* Member blocking of a truncation group (members sharing N and nlat). In FP64
+ * a group with several members runs its Legendre synthesis and analysis as
+ * FP64 MFMA products in which one pass over the table serves a block of
+ * members (the same sums as Section 4.2; the table entries are reused as the
+ * rows of a matrix product whose columns are the members' panels or ring
+ * spectra). synth_block is 0 (one member per workgroup, the single-member
+ * kernels) or 2, 4, 8, 16; anal_block is 0 or 2, 4, 8. The default is the
+ * largest power of two <= min(members, 8) for groups of >= 2 members, or what
+ * NSE_FLAG_AUTOTUNE measured. `member` selects the group by any of its
+ * members. Other precisions always use the single-member kernels. Setting
+ * drops captured graphs. NSE_ERR_ARG for an unknown block size or member. */
+nse_status nse_get_member_blocks(const nse_ctx* ctx, int32_t member,
+                                 int32_t* synth_block, int32_t* anal_block);
+nse_status nse_set_member_blocks(nse_ctx* ctx, int32_t member,
+                                 int32_t synth_block, int32_t anal_block);
 
 /* Rebinds the context to another hipStream_t (captured graphs are dropped). */
 nse_status nse_set_stream(nse_ctx* ctx, void* hip_stream);

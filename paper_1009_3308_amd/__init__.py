@@ -28,6 +28,7 @@ PREC_BF16X3 = 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
 
 FLAG_GRAPH = 1
+FLAG_AUTOTUNE = 2
 FLAG_CHECK_FINITE = 4
 
 # Every function the header declares (checked against include/nse_sphere.h by the tests).
@@ -36,7 +37,7 @@ EXPORTS = (
     "nse_state_count", "nse_member_grid", "nse_nonlinear", "nse_step",
     "nse_nonlinear_adjoint", "nse_step_adjoint", "nse_synthesize", "nse_legendre_values",
     "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
-    "nse_analyze_velocity",
+    "nse_analyze_velocity", "nse_get_member_blocks", "nse_set_member_blocks",
 )
 
 KERNEL_KINDS = {"synthesis": 0, "ring": 1, "analysis": 2}
@@ -86,6 +87,8 @@ def lib():
         "nse_step_adjoint": (st, [vp, dp, dp, i64, dp]),
         "nse_synthesize": (st, [vp, dp, dp]),
         "nse_analyze_velocity": (st, [vp, dp, dp]),
+        "nse_get_member_blocks": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "nse_set_member_blocks": (st, [vp, i32, i32, i32]),
         "nse_legendre_values": (st, [vp, i32, i32, dp]),
         "nse_sync": (st, [vp]),
         "nse_profile_enable": (st, [vp, i32]),
@@ -139,7 +142,7 @@ class Sphere:
 
     def __init__(self, members: Sequence[tuple], omega: float, dt: float, order: int = 2,
                  newton_iters: int = 1, precision: str = "fp64", graph: bool = False,
-                 check_finite: bool = False, stream=None):
+                 check_finite: bool = False, autotune: bool = False, stream=None):
         import torch
         L = lib()
         self.member_specs = [(int(N), int(nlat), float(nu)) for (N, nlat, nu) in members]
@@ -147,7 +150,8 @@ class Sphere:
                                                    self.member_specs])
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_CHECK_FINITE if check_finite else 0)
+        flags = ((FLAG_GRAPH if graph else 0) | (FLAG_CHECK_FINITE if check_finite else 0)
+                 | (FLAG_AUTOTUNE if autotune else 0))
         self.params = Params(float(omega), float(dt), int(order), int(newton_iters),
                              PRECISIONS[precision], flags)
         self.order = int(order)
@@ -247,6 +251,17 @@ class Sphere:
             res.append(out[o:o + s].view(3, nl, 2 * nl))
             o += s
         return res
+
+    def member_blocks(self, member: int = 0):
+        """(synthesis, analysis) member-block sizes of the member's group (0 = per member)."""
+        sb, ab = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().nse_get_member_blocks(self._handle(), member, ctypes.byref(sb),
+                                           ctypes.byref(ab)), self._h)
+        return sb.value, ab.value
+
+    def set_member_blocks(self, member: int, synth_block: int, anal_block: int):
+        _check(lib().nse_set_member_blocks(self._handle(), member, synth_block, anal_block),
+               self._h)
 
     def analyze_velocity(self, grids, out=None):
         """alpha = (u, Z)_M from per-member grids [>=2, nlat, M] (u_theta, u_phi first)."""

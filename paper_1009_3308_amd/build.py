@@ -26,6 +26,7 @@ SOURCES = [
     "analysis.hip",
     "contract_lp.hip",
     "adjoint.hip",
+    "ensemble.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

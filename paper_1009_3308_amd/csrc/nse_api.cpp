@@ -24,6 +24,7 @@ namespace {
 struct Group {
   int N = 0, nlat = 0, nh = 0, M = 0;
   int precision = NSE_PREC_FP64;
+  int mb_synth = 0, mb_anal = 0;     // member blocks of the batched kernels
   std::vector<int> members;          // global member indices
   std::vector<int64_t> offsets;      // complex-slot offsets of those members
   std::vector<double> nu;
@@ -41,6 +42,8 @@ struct Group {
   GroupView view() const {
     GroupView g{};
     g.precision = precision;
+    g.mb_synth = mb_synth;
+    g.mb_anal = mb_anal;
     g.N = N;
     g.nlat = nlat;
     g.nh = nh;
@@ -67,6 +70,7 @@ struct Group {
   GroupView member_view(int i) const {
     GroupView g = view();
     g.nb = 1;
+    g.mb_synth = g.mb_anal = 0;
     g.F = d_F + (int64_t)i * 4 * nlat * (N + 1);
     g.W = d_W + (int64_t)i * nlat * (N + 1);
     if (d_Fa) {
@@ -305,14 +309,96 @@ nse_status timed_launch(nse_ctx* c, int kind, F&& launch) {
 
 // FP64 and FP32 contractions run on the vector units (HBM-bound table streams);
 // the split-bf16 form runs on MFMA.
+// Groups of several FP64 members use the member-batched MFMA products.
 hipError_t launch_synth_any(const GroupView& v, const SynthInput& in, int mode, hipStream_t s) {
   if (v.precision == NSE_PREC_BF16X3) return launch_synthesis_lp(v, in, mode, v.precision, s);
+  if (v.precision == NSE_PREC_FP64 && mode == SYNTH_NONLINEAR && v.mb_synth >= 2)
+    return launch_synthesis_mb(v, in, v.mb_synth, s);
   return launch_synthesis(v, in, mode, s);
 }
 
 hipError_t launch_anal_any(const GroupView& v, const AnalOutput& out, hipStream_t s) {
   if (v.precision == NSE_PREC_BF16X3) return launch_analysis_lp(v, out, v.precision, s);
+  if (v.precision == NSE_PREC_FP64 && v.mb_anal >= 2) return launch_analysis_mb(v, out, v.mb_anal, s);
   return launch_analysis(v, out, s);
+}
+
+bool valid_synth_block(int B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == 16; }
+bool valid_anal_block(int B) { return B == 0 || B == 2 || B == 4 || B == 8; }
+
+int default_block(int nb) {
+  if (nb < 2) return 0;
+  int B = 2;
+  while (B * 2 <= nb && B * 2 <= 8) B *= 2;
+  return B;
+}
+
+// Times `reps` launches of `launch` on the context stream (after one warm-up).
+template <typename F>
+nse_status time_launches(nse_ctx* c, int reps, F&& launch, float* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  NSE_HIP(c, hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
+  return NSE_OK;
+}
+
+// Picks the fastest member blocks of every FP64 group with >= 2 members by
+// timing its synthesis and analysis (nonlinear mode) on a zero state.
+nse_status autotune_blocks(nse_ctx* c) {
+  double2* scratch = nullptr;
+  NSE_HIP(c, dalloc(&scratch, (size_t)c->state_count));
+  NSE_HIP(c, hipMemsetAsync(scratch, 0, sizeof(double2) * c->state_count, c->stream));
+  nse_status st = NSE_OK;
+  for (auto& g : c->groups) {
+    if (g.precision != NSE_PREC_FP64 || g.members.size() < 2 || st != NSE_OK) continue;
+    SynthInput in{};
+    in.nsrc = 1;
+    in.src[0] = scratch;
+    in.coef[0] = 1.0;
+    AnalOutput out{};
+    out.mode = ANAL_NONLINEAR;
+    out.n_out = c->d_iter;
+    out.state_count = c->state_count;
+    float best = 1e30f;
+    for (int B : {0, 2, 4, 8, 16}) {
+      if (B > 2 * (int)g.members.size()) continue;
+      GroupView v = g.view();
+      v.mb_synth = B;
+      float ms = 0.f;
+      st = time_launches(c, 5, [&] { return launch_synth_any(v, in, SYNTH_NONLINEAR, c->stream); },
+                         &ms);
+      if (st != NSE_OK) break;
+      if (ms < best) {
+        best = ms;
+        g.mb_synth = B;
+      }
+    }
+    best = 1e30f;
+    for (int B : {0, 2, 4, 8}) {
+      if (st != NSE_OK || B > 2 * (int)g.members.size()) continue;
+      GroupView v = g.view();
+      v.mb_anal = B;
+      float ms = 0.f;
+      st = time_launches(c, 5, [&] { return launch_anal_any(v, out, c->stream); }, &ms);
+      if (st != NSE_OK) break;
+      if (ms < best) {
+        best = ms;
+        g.mb_anal = B;
+      }
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(scratch);
+  return st;
 }
 
 // Enqueues one full evaluation chain (synthesis, ring, analysis) for every group.
@@ -463,7 +549,7 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
   if (P.precision != NSE_PREC_FP64 && P.precision != NSE_PREC_FP32 &&
       P.precision != NSE_PREC_BF16X3)
     return init_fail(NSE_ERR_ARG, "unknown precision");
-  if (P.flags & ~(uint32_t)(NSE_FLAG_GRAPH | NSE_FLAG_CHECK_FINITE))
+  if (P.flags & ~(uint32_t)(NSE_FLAG_GRAPH | NSE_FLAG_AUTOTUNE | NSE_FLAG_CHECK_FINITE))
     return init_fail(NSE_ERR_ARG, "unknown flag bits");
   if (!is_finite(P.omega)) return init_fail(NSE_ERR_ARG, "omega must be finite");
   if (!is_finite(P.dt) || !(P.dt > 0.0)) return init_fail(NSE_ERR_ARG, "dt must be finite and > 0");
@@ -541,6 +627,7 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
     c->groups[gi].nu.push_back(mem[i].nu);
   }
   c->state_count = off;
+  for (auto& g : c->groups) g.mb_synth = g.mb_anal = default_block((int)g.members.size());
 
   auto cleanup = [&](nse_status s) {
     for (auto& g : c->groups) free_group(g);
@@ -558,6 +645,10 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
   if (e == hipSuccess) e = hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return cleanup(hip_fail(c.get(), e, "init"));
+  if (P.flags & NSE_FLAG_AUTOTUNE) {
+    nse_status s = autotune_blocks(c.get());
+    if (s != NSE_OK) return cleanup(s);
+  }
   *out = c.release();
   return NSE_OK;
 }
@@ -578,6 +669,33 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_abar);
   (void)hipFree(ctx->d_hist_save);
   delete ctx;
+  return NSE_OK;
+}
+
+nse_status nse_get_member_blocks(const nse_ctx* ctx, int32_t member, int32_t* synth_block,
+                                 int32_t* anal_block) {
+  if (!ctx) return NSE_ERR_ARG;
+  nse_ctx* c = const_cast<nse_ctx*>(ctx);
+  if (member < 0 || member >= (int)ctx->members.size())
+    return fail(c, NSE_ERR_ARG, "member %d out of range", member);
+  const Group& g = ctx->groups[ctx->member_group[member]];
+  if (synth_block) *synth_block = g.mb_synth;
+  if (anal_block) *anal_block = g.mb_anal;
+  return NSE_OK;
+}
+
+nse_status nse_set_member_blocks(nse_ctx* ctx, int32_t member, int32_t synth_block,
+                                 int32_t anal_block) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (member < 0 || member >= (int)ctx->members.size())
+    return fail(ctx, NSE_ERR_ARG, "member %d out of range", member);
+  if (!valid_synth_block(synth_block) || !valid_anal_block(anal_block))
+    return fail(ctx, NSE_ERR_ARG, "member blocks (%d, %d): synthesis takes 0, 2, 4, 8, 16 and "
+                "analysis 0, 2, 4, 8", synth_block, anal_block);
+  Group& g = ctx->groups[ctx->member_group[member]];
+  g.mb_synth = synth_block;
+  g.mb_anal = anal_block;
+  drop_graphs(ctx);
   return NSE_OK;
 }
 

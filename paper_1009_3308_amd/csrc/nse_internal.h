@@ -51,6 +51,7 @@ __host__ __device__ inline int64_t t1_size(int N, int nh) {
 struct GroupView {
   int N, nlat, nh, M, nb;   // nh = northern latitudes incl. the equator if nlat is odd
   int precision;            // NSE_PREC_* of the Legendre contractions
+  int mb_synth, mb_anal;    // member blocks of the batched FP64 MFMA kernels (0 = per member)
   const double* mu;         // [nh] Gauss-Legendre nodes, descending
   const double* w;          // [nh]
   const double* T1;         // FP64 synthesis table (layouts above)
@@ -119,6 +120,8 @@ hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, dou
 hipError_t launch_step_adjoint_post(const GroupView& g, const SynthInput& pred,
                                     int64_t state_count, double2* hist_bar, const double2* abar,
                                     hipStream_t s);
+hipError_t launch_synthesis_mb(const GroupView& g, const SynthInput& in, int B, hipStream_t s);
+hipError_t launch_analysis_mb(const GroupView& g, const AnalOutput& out, int B, hipStream_t s);
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
                                hipStream_t s);
 hipError_t launch_analysis_lp(const GroupView& g, const AnalOutput& out, int prec, hipStream_t s);

@@ -224,8 +224,10 @@ def test_graph_replay_equals_eager_bitwise():
 
 def test_multi_member_context_equals_single_members():
     specs = [(31, 0, 1e-3), (63, 0, 1e-4), (31, 0, 5e-4), (15, 30, 2e-3)]
-    _say("case: multi-member context")
+    _say("case: multi-member context (per-member kernels)")
     multi = pkg.Sphere(specs, omega=OMEGA, dt=1e-3)
+    for i in range(len(specs)):
+        multi.set_member_blocks(i, 0, 0)  # the batched products are tested in test_gpu_ensemble
     states = [I.member_state(i, N) for i, (N, _, _) in enumerate(specs)]
     forc = [I.spectrum(200 + i, N, 1e-2) for i, (N, _, _) in enumerate(specs)]
     a = pkg.to_device(np.concatenate(states))
