@@ -20,6 +20,8 @@
 // a radix-R butterfly and writes back in autosort order after a barrier. The
 // two inverse transforms run in the same stages. With the odd radices last,
 // the stage strides are powers of two and the index arithmetic is shifts.
+#include <type_traits>
+
 #include "nse_internal.h"
 
 namespace nse {
@@ -190,6 +192,93 @@ __device__ void fft(double2* x0, double2* x1, const FftPlan& plan, int M, const 
   }
 }
 
+// Compile-time plans for M = 3 * 2^k, the default grid of every truncation
+// (M = 3(N+1) for N = 2^j - 1): radix-8 stages (radix 4 where the power of
+// two needs it), radix 3 last, so every stride before the last stage is a
+// power of two. With M, the radices, the strides and the direction known at
+// compile time, the index arithmetic of a stage folds into constants.
+template <int M> struct CtPlan { static constexpr int n = 0; static constexpr int r[1] = {0}; };
+template <> struct CtPlan<48> { static constexpr int n = 3; static constexpr int r[3] = {4, 4, 3}; };
+template <> struct CtPlan<96> { static constexpr int n = 3; static constexpr int r[3] = {8, 4, 3}; };
+template <> struct CtPlan<192> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 3}; };
+template <> struct CtPlan<384> { static constexpr int n = 4; static constexpr int r[4] = {8, 4, 4, 3}; };
+template <> struct CtPlan<768> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 4, 3}; };
+template <> struct CtPlan<1536> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 8, 3}; };
+
+constexpr int ct_log2(int x) { return x <= 1 ? 0 : 1 + ct_log2(x / 2); }
+
+// One Stockham stage of radix R at stride NS (a power of two) on NA arrays of
+// length M (x1 = x0 + padded_len(M) when NA = 2); SGN = -1 forward, +1 inverse.
+template <int R, int NS, int M, int NA, int NT, int SGN>
+__device__ __forceinline__ void stage_ct(double2* x0, const double2* tw) {
+  constexpr int span = M / R, total = span * NA, MAXB = (total + NT - 1) / NT;
+  constexpr int step = M / (NS * R), half = M / 2, lg = ct_log2(NS);
+  constexpr int PL = M + (M >> 4) + 1;
+  double2 v[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int t = threadIdx.x + c * NT;
+    dst[c] = -1;
+    if (total % NT == 0 || t < total) {
+      const int a = (NA == 1) ? 0 : (t >= span ? 1 : 0);
+      const int j = t - a * span;
+      const double2* x = x0 + a * PL;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = x[pad(j + r * span)];
+      const int k = j & (NS - 1), q = j >> lg;
+      if constexpr (NS > 1) {
+        const int ks = k * step;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int e = r * ks;  // < M
+          double2 w = tw[e < half ? e : e - half];
+          if (e >= half) w = make_double2(-w.x, -w.y);
+          if (SGN > 0) w.y = -w.y;  // the table holds exp(-2 pi i e / M)
+          v[c][r] = cmul(v[c][r], w);
+        }
+      }
+      butterfly<R>(v[c], (double)SGN);
+      dst[c] = a * PL + q * NS * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (dst[c] >= 0) {
+      const int base = dst[c] >= PL ? PL : 0;
+      const int idx = dst[c] - base;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x0[base + pad(idx + r * NS)] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int M, int S, int NS, int NA, int NT, int SGN>
+__device__ __forceinline__ void stages_ct(double2* x0, const double2* tw) {
+  if constexpr (S < CtPlan<M>::n) {
+    constexpr int R = CtPlan<M>::r[S];
+    stage_ct<R, NS, M, NA, NT, SGN>(x0, tw);
+    stages_ct<M, S + 1, NS * R, NA, NT, SGN>(x0, tw);
+  }
+}
+
+// Transform of one or two LDS arrays (x1 must be x0 + padded_len(M) when
+// NA = 2): the compile-time plan when CM > 0, else the runtime plan.
+template <int NA, int MAXM, int NT, int CM>
+__device__ __forceinline__ void fft_any(double2* x0, double2* x1, const FftPlan& plan, int M,
+                                        const double2* tw, double sign) {
+  if constexpr (CM > 0) {
+    if (sign > 0)
+      stages_ct<CM, 0, 1, NA, NT, 1>(x0, tw);
+    else
+      stages_ct<CM, 0, 1, NA, NT, -1>(x0, tw);
+  } else {
+    fft<NA, MAXM, NT>(x0, x1, plan, M, tw, sign);
+  }
+}
+
 // Spectrum of the field pair (a, b) of one ring into x[0..M):
 // x_m = G^a_m + i G^b_m, x_{M-m} = conj(G^a_m) + i conj(G^b_m), zero elsewhere.
 // G[m] is read from F[f][m][lat] (stride nlat between orders).
@@ -232,11 +321,11 @@ size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(
 // neighbouring latitudes so that the strided reads of F share L2 lines.
 // MAXM: the largest M of the size class this instance serves and NT its
 // workgroup size (register arrays are sized from both).
-template <int MAXM, int NT>
+template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode,
                                              double* grid_out) {
   constexpr int PTS = (MAXM + NT - 1) / NT;
-  const int N = g.N, M = g.M, nlat = g.nlat;
+  const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
   const int lat = xcd_item(blockIdx.x, 8);
   if (lat >= nlat) return;
   const int b = blockIdx.y;
@@ -258,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     load_pair(A0, F0, F0 + fstride, lat, N, M, nlat);
     load_pair(A1, F0 + 2 * fstride, F0 + 2 * fstride, lat, N, M, nlat);
     __syncthreads();
-    fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+    fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
     double* g0 = grid_out + ((int64_t)0 * nlat + lat) * M;
     double* g1 = grid_out + ((int64_t)1 * nlat + lat) * M;
     double* g2 = grid_out + ((int64_t)2 * nlat + lat) * M;
@@ -275,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   load_pair(A0, F0, F0 + 2 * fstride, lat, N, M, nlat);
   load_pair(A1, F0 + fstride, F0 + 3 * fstride, lat, N, M, nlat);
   __syncthreads();
-  fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+  fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   const double inv_sin2 = 1.0 / sin2;
   double q[PTS];
 #pragma unroll
@@ -294,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     if (j < M) A0[pad(j)] = make_double2(q[c], 0.0);
   }
   __syncthreads();
-  fft<1, MAXM, NT>(A0, A1, plan, M, tw, -1.0);
+  fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
   // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
   // own mirror and is folded twice by the analysis
   const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
@@ -314,10 +403,10 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
 // and the cotangents of the field spectra (the c2r of the synthesis)^T:
 //   Gbar_0 = sum_j gbar_j,  Gbar_m = 2 sum_j gbar_j e^{-i m phi_j}  (m >= 1),
 // written to Fbar[b][f][lat][m]. c_lat = (2 pi / M) w_p.
-template <int MAXM, int NT>
+template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   constexpr int PTS = (MAXM + NT - 1) / NT;
-  const int N = g.N, M = g.M, nlat = g.nlat;
+  const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
   const int lat = blockIdx.x;
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;
@@ -336,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   load_pair(A0, F5, F5 + 2 * fstride, lat, N, M, nlat);
   load_pair(A1, F5 + fstride, F5 + 3 * fstride, lat, N, M, nlat);
   __syncthreads();
-  fft<2, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+  fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   double g0[PTS], g1[PTS], g2[PTS], g3[PTS];
 #pragma unroll
   for (int c = 0; c < PTS; ++c) {
@@ -354,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   // cotangent of the grid product
   load_single(A0, F5 + 4 * fstride, 0.5, lat, N, M, nlat);
   __syncthreads();
-  fft<1, MAXM, NT>(A0, A1, plan, M, tw, 1.0);
+  fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   const double clat = (6.283185307179586477 / M) * g.w[p];
   double qb[PTS];
 #pragma unroll
@@ -372,7 +461,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
     }
   }
   __syncthreads();
-  fft<2, MAXM, NT>(A0, A1, plan, M, tw, -1.0);
+  fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
   // unpack two real transforms per array: z = a + i b ->
   // A_m = (Z_m + conj Z_{M-m}) / 2, B_m = (Z_m - conj Z_{M-m}) / (2 i); times 2 for m >= 1
   double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
@@ -399,10 +488,10 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
 // coupling of d/dtheta are done by the unweighted analysis and the prologue
 // transpose, since conj(Z[l,m]) = lambda^(-1/2) (-i m Pbar / sin, -dPbar/dtheta) e^{-i m phi}
 // and sin(theta) dPbar/dtheta couples degrees l - 1 and l + 1.
-template <int MAXM, int NT>
+template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
                                                      const double* __restrict__ u_grid) {
-  const int N = g.N, M = g.M, nlat = g.nlat;
+  const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
   const int lat = blockIdx.x;
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;
@@ -415,7 +504,7 @@ __global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
   const double* up = ut + (int64_t)nlat * M;
   for (int j = threadIdx.x; j < M; j += blockDim.x) A0[pad(j)] = make_double2(ut[j], up[j]);
   __syncthreads();
-  fft<1, MAXM, NT>(A0, A0, plan, M, tw, -1.0);
+  fft_any<1, MAXM, NT, CM>(A0, A0, plan, M, tw, -1.0);
   const double x = g.mu[p];
   const double c = (6.283185307179586477 / M) * g.w[p] / sqrt((1.0 - x) * (1.0 + x));
   const int64_t fstride = (int64_t)(N + 1) * nlat;
@@ -431,54 +520,58 @@ __global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
   }
 }
 
+// Calls launch(MAXM, NT, CM) (as integral constants) for the group's M: the
+// compile-time instance when M = 3 * 2^k is one of the default grids, else
+// the size class of the runtime plan.
+template <typename F>
+hipError_t ring_dispatch(int M, F&& launch) {
+  using std::integral_constant;
+  switch (M) {
+    case 48: return launch(integral_constant<int, 48>{}, integral_constant<int, 64>{}, integral_constant<int, 48>{});
+    case 96: return launch(integral_constant<int, 96>{}, integral_constant<int, 64>{}, integral_constant<int, 96>{});
+    case 192: return launch(integral_constant<int, 192>{}, integral_constant<int, 128>{}, integral_constant<int, 192>{});
+    case 384: return launch(integral_constant<int, 384>{}, integral_constant<int, 128>{}, integral_constant<int, 384>{});
+    case 768: return launch(integral_constant<int, 768>{}, integral_constant<int, 256>{}, integral_constant<int, 768>{});
+    case 1536: return launch(integral_constant<int, 1536>{}, integral_constant<int, 512>{}, integral_constant<int, 1536>{});
+    default: break;
+  }
+  if (M <= 256) return launch(integral_constant<int, 256>{}, integral_constant<int, 128>{}, integral_constant<int, 0>{});
+  if (M <= 512) return launch(integral_constant<int, 512>{}, integral_constant<int, 256>{}, integral_constant<int, 0>{});
+  if (M <= 768) return launch(integral_constant<int, 768>{}, integral_constant<int, 256>{}, integral_constant<int, 0>{});
+  if (M <= 1024) return launch(integral_constant<int, 1024>{}, integral_constant<int, 512>{}, integral_constant<int, 0>{});
+  return launch(integral_constant<int, kMaxM>{}, integral_constant<int, 512>{}, integral_constant<int, 0>{});
+}
+
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
   dim3 grid(g.nlat, g.nb);
   const size_t lds = ring_lds_bytes(g.M);
-  if (g.M <= 256)
-    hipLaunchKernelGGL((k_ring_adj<256, 128>), grid, dim3(128), lds, s, g, plan);
-  else if (g.M <= 512)
-    hipLaunchKernelGGL((k_ring_adj<512, 256>), grid, dim3(256), lds, s, g, plan);
-  else if (g.M <= 768)
-    hipLaunchKernelGGL((k_ring_adj<768, 256>), grid, dim3(256), lds, s, g, plan);
-  else if (g.M <= 1024)
-    hipLaunchKernelGGL((k_ring_adj<1024, 512>), grid, dim3(512), lds, s, g, plan);
-  else
-    hipLaunchKernelGGL((k_ring_adj<kMaxM, 512>), grid, dim3(512), lds, s, g, plan);
-  return hipGetLastError();
+  return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
+    constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
+    hipLaunchKernelGGL((k_ring_adj<MAXM, NT, CM>), grid, dim3(NT), lds, s, g, plan);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const double* u_grid,
                                hipStream_t s) {
   dim3 grid(g.nlat, g.nb);
   const size_t lds = ring_lds_bytes(g.M);
-  if (g.M <= 256)
-    hipLaunchKernelGGL((k_ring_project<256, 128>), grid, dim3(128), lds, s, g, plan, u_grid);
-  else if (g.M <= 512)
-    hipLaunchKernelGGL((k_ring_project<512, 256>), grid, dim3(256), lds, s, g, plan, u_grid);
-  else if (g.M <= 768)
-    hipLaunchKernelGGL((k_ring_project<768, 256>), grid, dim3(256), lds, s, g, plan, u_grid);
-  else if (g.M <= 1024)
-    hipLaunchKernelGGL((k_ring_project<1024, 512>), grid, dim3(512), lds, s, g, plan, u_grid);
-  else
-    hipLaunchKernelGGL((k_ring_project<kMaxM, 512>), grid, dim3(512), lds, s, g, plan, u_grid);
-  return hipGetLastError();
+  return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
+    constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
+    hipLaunchKernelGGL((k_ring_project<MAXM, NT, CM>), grid, dim3(NT), lds, s, g, plan, u_grid);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
   const size_t lds = ring_lds_bytes(g.M);
-  if (g.M <= 256)
-    hipLaunchKernelGGL((k_ring<256, 128>), grid, dim3(128), lds, s, g, plan, mode, grid_out);
-  else if (g.M <= 512)
-    hipLaunchKernelGGL((k_ring<512, 256>), grid, dim3(256), lds, s, g, plan, mode, grid_out);
-  else if (g.M <= 768)
-    hipLaunchKernelGGL((k_ring<768, 256>), grid, dim3(256), lds, s, g, plan, mode, grid_out);
-  else if (g.M <= 1024)
-    hipLaunchKernelGGL((k_ring<1024, 512>), grid, dim3(512), lds, s, g, plan, mode, grid_out);
-  else
-    hipLaunchKernelGGL((k_ring<kMaxM, 512>), grid, dim3(512), lds, s, g, plan, mode, grid_out);
-  return hipGetLastError();
+  return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
+    constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
+    hipLaunchKernelGGL((k_ring<MAXM, NT, CM>), grid, dim3(NT), lds, s, g, plan, mode, grid_out);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace nse
