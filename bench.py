@@ -189,8 +189,9 @@ def adjoint_timing(pkg, torch, N, nu, steps, every=20, reps=3):
 def ensemble_timing(pkg, torch, steps=100, warmup=10):
     """Mixed-truncation ensemble (24 x N=63, 24 x N=127, 16 x N=255; nu log-uniform in
     [1e-5, 1e-3]; Omega = 2 pi, dt = 1e-3, NDF2): member-steps/s of one context that steps
-    all members (one graph per 10-step chunk holding every group's kernels), and of the same
-    members stepped one context per member (per-member launches), both after `warmup` steps."""
+    all members (one graph per 10-step chunk holding every group's kernels; member blocks of
+    the batched MFMA contractions autotuned at init), and of the same members stepped one
+    context per member (per-member launches), both after `warmup` steps."""
     import nse_inputs as I
     Ns = I.ensemble_truncations()
     nus = I.ensemble_viscosities(len(Ns))
@@ -198,7 +199,9 @@ def ensemble_timing(pkg, torch, steps=100, warmup=10):
     stream = torch.cuda.Stream()
     out = {}
     with torch.cuda.stream(stream):
-        s = pkg.Sphere(specs, omega=2 * math.pi, dt=1e-3, graph=True, stream=stream)
+        s = pkg.Sphere(specs, omega=2 * math.pi, dt=1e-3, graph=True, autotune=True,
+                       stream=stream)
+        out["member_blocks"] = {f"N={specs[i][0]}": list(s.member_blocks(i)) for i in (0, 24, 48)}
         h, f = s.new_history(), s.new_state()
         for i, (N, _, _) in enumerate(specs):
             h[0, s.member_slice(i)] = pkg.to_device(I.member_state(i, N))
@@ -231,6 +234,7 @@ def ensemble_timing(pkg, torch, steps=100, warmup=10):
             c.close()
     n = len(specs)
     out["members"] = n
+    out["truncations"] = "24 x N=63, 24 x N=127, 16 x N=255"
     out["member_steps_per_s"] = round(n * steps / t_one, 1)
     out["ms_per_step"] = round(1e3 * t_one / steps, 4)
     out["per_member_contexts_member_steps_per_s"] = round(n * steps / t_sep, 1)
@@ -250,6 +254,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-t511", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB read + 256 MiB write kernel, the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -339,6 +344,12 @@ def main():
                     extra[f"t511_{prec}_steps_per_s"] / extra["t511_fp64_steps_per_s"], 3)
         log("bench: T511 precision errors (200 steps)")
         extra.update({f"t511_{k}": v for k, v in precision_errors(pkg, torch, 511, 1e-5, 200).items()})
+
+    if not args.no_ensemble:
+        log("bench: mixed-truncation ensemble, 64 members, 100 steps")
+        ens = ensemble_timing(pkg, torch)
+        extra["ensemble"] = ens
+        log(f"bench: ensemble {ens}")
 
     if not args.no_adjoint:
         log("bench: T255 adjoint, 200 steps, checkpoints every 20")
