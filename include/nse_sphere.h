@@ -114,12 +114,13 @@ nse_status nse_sphere_destroy(nse_ctx* ctx);
  * FP64 MFMA products in which one pass over the table serves a block of
  * members (the same sums as Section 4.2; the table entries are reused as the
  * rows of a matrix product whose columns are the members' panels or ring
- * spectra). synth_block is 0 (one member per workgroup, the single-member
- * kernels) or 2, 4, 8, 16; anal_block is 0 or 2, 4, 8. The default is the
- * largest power of two <= min(members, 8) for groups of >= 2 members, or what
- * NSE_FLAG_AUTOTUNE measured. `member` selects the group by any of its
+ * spectra). synth_block and anal_block are 0 (one member per workgroup, the
+ * single-member kernels) or 2, 4, 8. The default for FP64 groups of >= 2
+ * members is the largest power of two <= min(members, 4) for the synthesis
+ * and <= min(members, 8) for the analysis, or what NSE_FLAG_AUTOTUNE measured. `member` selects the group by any of its
  * members. Other precisions always use the single-member kernels. Setting
- * drops captured graphs. NSE_ERR_ARG for an unknown block size or member. */
+ * drops captured graphs. NSE_ERR_ARG for an unknown block size or member, or
+ * for non-zero blocks on a group of one member or of another precision. */
 nse_status nse_get_member_blocks(const nse_ctx* ctx, int32_t member,
                                  int32_t* synth_block, int32_t* anal_block);
 nse_status nse_set_member_blocks(nse_ctx* ctx, int32_t member,

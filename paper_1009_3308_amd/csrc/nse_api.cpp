@@ -332,13 +332,14 @@ hipError_t launch_anal_any(const GroupView& v, const AnalOutput& out, hipStream_
   return launch_analysis(v, out, s);
 }
 
-bool valid_synth_block(int B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == 16; }
+bool valid_synth_block(int B) { return B == 0 || B == 2 || B == 4 || B == 8; }
 bool valid_anal_block(int B) { return B == 0 || B == 2 || B == 4 || B == 8; }
 
-int default_block(int nb) {
+// Largest power of two <= min(nb, cap) for groups of >= 2 members, else 0.
+int default_block(int nb, int cap) {
   if (nb < 2) return 0;
   int B = 2;
-  while (B * 2 <= nb && B * 2 <= 8) B *= 2;
+  while (B * 2 <= nb && B * 2 <= cap) B *= 2;
   return B;
 }
 
@@ -378,7 +379,7 @@ nse_status autotune_blocks(nse_ctx* c) {
     out.n_out = c->d_iter;
     out.state_count = c->state_count;
     float best = 1e30f;
-    for (int B : {0, 2, 4, 8, 16}) {
+    for (int B : {0, 2, 4, 8}) {
       if (B > 2 * (int)g.members.size()) continue;
       GroupView v = g.view();
       v.mb_synth = B;
@@ -636,7 +637,11 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
     c->groups[gi].nu.push_back(mem[i].nu);
   }
   c->state_count = off;
-  for (auto& g : c->groups) g.mb_synth = g.mb_anal = default_block((int)g.members.size());
+  for (auto& g : c->groups) {
+    if (g.precision != NSE_PREC_FP64) continue;
+    g.mb_synth = default_block((int)g.members.size(), 4);
+    g.mb_anal = default_block((int)g.members.size(), 8);
+  }
 
   auto cleanup = [&](nse_status s) {
     for (auto& g : c->groups) free_group(g);
@@ -699,9 +704,11 @@ nse_status nse_set_member_blocks(nse_ctx* ctx, int32_t member, int32_t synth_blo
   if (member < 0 || member >= (int)ctx->members.size())
     return fail(ctx, NSE_ERR_ARG, "member %d out of range", member);
   if (!valid_synth_block(synth_block) || !valid_anal_block(anal_block))
-    return fail(ctx, NSE_ERR_ARG, "member blocks (%d, %d): synthesis takes 0, 2, 4, 8, 16 and "
-                "analysis 0, 2, 4, 8", synth_block, anal_block);
+    return fail(ctx, NSE_ERR_ARG, "member blocks (%d, %d): both take 0, 2, 4 or 8", synth_block,
+                anal_block);
   Group& g = ctx->groups[ctx->member_group[member]];
+  if ((synth_block || anal_block) && (g.members.size() < 2 || g.precision != NSE_PREC_FP64))
+    return fail(ctx, NSE_ERR_ARG, "member blocks need an FP64 group of at least two members");
   g.mb_synth = synth_block;
   g.mb_anal = anal_block;
   drop_graphs(ctx);

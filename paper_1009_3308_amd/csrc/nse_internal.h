@@ -24,6 +24,15 @@ __host__ __device__ inline int xcd_item(int bid, int chunk) {
   const int x = bid & 7, k = bid >> 3;
   return ((x + 8 * (k / chunk)) * chunk) + (k % chunk);
 }
+// As xcd_item, with the XCD order reversed on every other round of chunks, so
+// that when the cost of a chunk falls with its index (orders m of decreasing
+// degree count) every XCD gets a similar share.
+__host__ __device__ inline int xcd_item_snake(int bid, int chunk) {
+  const int x = bid & 7, k = bid >> 3;
+  const int round = k / chunk;
+  const int xs = (round & 1) ? 7 - x : x;
+  return ((xs + 8 * round) * chunk) + (k % chunk);
+}
 // Grid size covering `items` work items for xcd_item (a multiple of 8 * chunk).
 __host__ __device__ inline int xcd_grid(int items, int chunk) {
   const int per = 8 * chunk;
