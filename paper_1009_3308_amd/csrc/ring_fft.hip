@@ -530,9 +530,9 @@ hipError_t ring_dispatch(int M, F&& launch) {
     case 48: return launch(integral_constant<int, 48>{}, integral_constant<int, 64>{}, integral_constant<int, 48>{});
     case 96: return launch(integral_constant<int, 96>{}, integral_constant<int, 64>{}, integral_constant<int, 96>{});
     case 192: return launch(integral_constant<int, 192>{}, integral_constant<int, 128>{}, integral_constant<int, 192>{});
-    case 384: return launch(integral_constant<int, 384>{}, integral_constant<int, 128>{}, integral_constant<int, 384>{});
-    case 768: return launch(integral_constant<int, 768>{}, integral_constant<int, 256>{}, integral_constant<int, 768>{});
-    case 1536: return launch(integral_constant<int, 1536>{}, integral_constant<int, 512>{}, integral_constant<int, 1536>{});
+    case 384: return launch(integral_constant<int, 384>{}, integral_constant<int, 256>{}, integral_constant<int, 384>{});
+    case 768: return launch(integral_constant<int, 768>{}, integral_constant<int, 512>{}, integral_constant<int, 768>{});
+    case 1536: return launch(integral_constant<int, 1536>{}, integral_constant<int, 1024>{}, integral_constant<int, 1536>{});
     default: break;
   }
   if (M <= 256) return launch(integral_constant<int, 256>{}, integral_constant<int, 128>{}, integral_constant<int, 0>{});
