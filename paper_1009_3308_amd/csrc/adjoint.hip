@@ -21,6 +21,7 @@ namespace nse {
 
 constexpr int kAdjWaves = 4;
 constexpr int kAdjThreads = 64 * kAdjWaves;
+constexpr int kAdjBatch = 8;  // table rows per load batch
 
 size_t synthesis_adjoint_lds_bytes(int nh) {
   // folded cotangents [4 fields][2 parities][nh], reused for the cross-wave sums
@@ -68,13 +69,31 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) 
   if (k < L) {
     const int par = k & 1;
     const double* t = g.T2 + g.t2off[m] + (int64_t)tile * nh * kTile + lane;
-    for (int p = p0; p < p1; ++p) {
-      const double tv = t[(int64_t)p * kTile];
+    // batches of kAdjBatch latitudes; the next batch's table loads are issued
+    // before the current batch's FMAs
+    double tn[kAdjBatch];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const double2 w = fsh[(2 * f + par) * nh + p];
-        acc[2 * f + 0] = fma(tv, w.x, acc[2 * f + 0]);
-        acc[2 * f + 1] = fma(tv, w.y, acc[2 * f + 1]);
+    for (int u = 0; u < kAdjBatch; ++u) tn[u] = (p0 + u < p1) ? t[(int64_t)(p0 + u) * kTile] : 0.0;
+    for (int pb = p0; pb < p1; pb += kAdjBatch) {
+      double tc[kAdjBatch];
+#pragma unroll
+      for (int u = 0; u < kAdjBatch; ++u) tc[u] = tn[u];
+#pragma unroll
+      for (int u = 0; u < kAdjBatch; ++u) {
+        const int p = pb + kAdjBatch + u;
+        tn[u] = (p < p1) ? t[(int64_t)p * kTile] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kAdjBatch; ++u) {
+        const int p = pb + u;
+        if (p < p1) {
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            const double2 w = fsh[(2 * f + par) * nh + p];
+            acc[2 * f + 0] = fma(tc[u], w.x, acc[2 * f + 0]);
+            acc[2 * f + 1] = fma(tc[u], w.y, acc[2 * f + 1]);
+          }
+        }
       }
     }
   }
@@ -97,41 +116,42 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) 
   }
 }
 
+// alpha_bar at degree l = m + k of member b from the panel cotangents of
+// order m (P = Pbar[b][m][k][f]): the transposed panel recurrences above.
+__device__ inline double2 alpha_bar_at(const GroupView& g, const double2* P, int m, int k) {
+  const int N = g.N, L = N + 2 - m, l = m + k;
+  if (l < 1) return make_double2(0.0, 0.0);
+  const double dm = (double)m;
+  auto e_of = [&](int ll) -> double {
+    return (ll > m) ? sqrt(((double)ll * ll - dm * dm) / (4.0 * (double)ll * ll - 1.0)) : 0.0;
+  };
+  double2 psib = make_double2(dm * P[4 * k + 0].y, -dm * P[4 * k + 0].x);  // -i m f0_bar
+  double2 zetb = make_double2(dm * P[4 * k + 3].y, -dm * P[4 * k + 3].x);  // -i m f3_bar
+  if (k + 1 < L) {
+    const double cmn = (double)l * e_of(l + 1);  // cm(k+1)
+    psib.x += cmn * P[4 * (k + 1) + 1].x;
+    psib.y += cmn * P[4 * (k + 1) + 1].y;
+    zetb.x += cmn * P[4 * (k + 1) + 2].x;
+    zetb.y += cmn * P[4 * (k + 1) + 2].y;
+  }
+  if (k >= 1) {
+    const double cpp = (double)(l + 1) * e_of(l);  // cp(k-1)
+    psib.x -= cpp * P[4 * (k - 1) + 1].x;
+    psib.y -= cpp * P[4 * (k - 1) + 1].y;
+    zetb.x -= cpp * P[4 * (k - 1) + 2].x;
+    zetb.y -= cpp * P[4 * (k - 1) + 2].y;
+  }
+  const double sq = sqrt((double)l * (l + 1));
+  return make_double2(psib.x / sq + zetb.x * sq, m == 0 ? 0.0 : psib.y / sq + zetb.y * sq);
+}
+
 // One workgroup per (order m, member); one thread per degree l = m..N.
 __global__ __launch_bounds__(256) void k_prep_adjoint(GroupView g, double2* alpha_bar) {
   const int N = g.N;
   const int m = blockIdx.x, b = blockIdx.y;
-  const int L = N + 2 - m;
-  const double dm = (double)m;
   const double2* P = g.Pbar + ((int64_t)b * (N + 1) + m) * (N + 2) * 4;  // [k][f]
-  auto e_of = [&](int l) -> double {
-    return (l > m) ? sqrt(((double)l * l - dm * dm) / (4.0 * (double)l * l - 1.0)) : 0.0;
-  };
-  for (int k = threadIdx.x; k <= N - m; k += blockDim.x) {
-    const int l = m + k;
-    double2 out = make_double2(0.0, 0.0);
-    if (l >= 1) {
-      double2 psib = make_double2(dm * P[4 * k + 0].y, -dm * P[4 * k + 0].x);   // -i m f0_bar
-      double2 zetb = make_double2(dm * P[4 * k + 3].y, -dm * P[4 * k + 3].x);   // -i m f3_bar
-      if (k + 1 < L) {
-        const double cmn = (double)(l + 1 - 1) * e_of(l + 1);  // cm(k+1)
-        psib.x += cmn * P[4 * (k + 1) + 1].x;
-        psib.y += cmn * P[4 * (k + 1) + 1].y;
-        zetb.x += cmn * P[4 * (k + 1) + 2].x;
-        zetb.y += cmn * P[4 * (k + 1) + 2].y;
-      }
-      if (k >= 1) {
-        const double cpp = (double)(l - 1 + 2) * e_of(l);  // cp(k-1)
-        psib.x -= cpp * P[4 * (k - 1) + 1].x;
-        psib.y -= cpp * P[4 * (k - 1) + 1].y;
-        zetb.x -= cpp * P[4 * (k - 1) + 2].x;
-        zetb.y -= cpp * P[4 * (k - 1) + 2].y;
-      }
-      const double sq = sqrt((double)l * (l + 1));
-      out = make_double2(psib.x / sq + zetb.x * sq, m == 0 ? 0.0 : psib.y / sq + zetb.y * sq);
-    }
-    alpha_bar[g.off[b] + coeff_offset(N, m) + k] = out;
-  }
+  for (int k = threadIdx.x; k <= N - m; k += blockDim.x)
+    alpha_bar[g.off[b] + coeff_offset(N, m) + k] = alpha_bar_at(g, P, m, k);
 }
 
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s) {
@@ -148,17 +168,22 @@ hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream
   return hipGetLastError();
 }
 
-// Element-wise part of the adjoint of one step, before the nonlinear adjoint:
-// with r = hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0),
-//   n_bar = -h r,  hbar_in[j] = hbar_out[j+1] - c_{j+1} r   (j = 0 .. depth-1),
-// written in place over hist_bar.
-__global__ __launch_bounds__(256) void k_step_adjoint_pre(GroupView g, AnalOutput st,
-                                                          double2* hist_bar, double2* nbar) {
+// The adjoint of one step after the nonlinear adjoint at the predictor, one
+// thread per (order m, degree k), in place over hist_bar: with
+// r = hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0) and
+// alpha_bar the predictor cotangent from the panel cotangents,
+//   hbar_in[j] = hbar_out[j+1] - c_{j+1} r + pi_j alpha_bar,   j = 0 .. depth-1.
+// (The cotangent of the nonlinear term, n_bar = -h r, was formed inside the
+// five-field synthesis from the same hbar_out[0].)
+__global__ __launch_bounds__(256) void k_prep_step_adjoint(GroupView g, AnalOutput st,
+                                                           SynthInput pred, double2* hist_bar) {
   const int N = g.N;
   const int m = blockIdx.x, b = blockIdx.z;
   const int k = blockIdx.y * blockDim.x + threadIdx.x;
   if (k > N - m) return;
   const int l = m + k;
+  const double2* P = g.Pbar + ((int64_t)b * (N + 1) + m) * (N + 2) * 4;
+  const double2 ab = alpha_bar_at(g, P, m, k);
   const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
   const double lam = (double)l * (l + 1);
   const double denom = st.c[0] + st.h * g.nu[b] * lam;
@@ -166,7 +191,6 @@ __global__ __launch_bounds__(256) void k_step_adjoint_pre(GroupView g, AnalOutpu
   r = make_double2(r.x / denom, r.y / denom);
   if (l == 0) r = make_double2(0.0, 0.0);
   if (m == 0) r.y = 0.0;
-  nbar[slot] = make_double2(-st.h * r.x, -st.h * r.y);
   double2 hb[kMaxStepCoef];
 #pragma unroll
   for (int j = 0; j < kMaxStepCoef; ++j) {
@@ -176,47 +200,20 @@ __global__ __launch_bounds__(256) void k_step_adjoint_pre(GroupView g, AnalOutpu
       hb[j].x -= st.c[j + 1] * r.x;
       hb[j].y -= st.c[j + 1] * r.y;
     }
+    if (j < pred.nsrc) {
+      hb[j].x += pred.coef[j] * ab.x;
+      hb[j].y += pred.coef[j] * ab.y;
+    }
   }
 #pragma unroll
   for (int j = 0; j < kMaxStepCoef; ++j)
     if (j < st.depth) hist_bar[(int64_t)j * st.state_count + slot] = hb[j];
 }
 
-// After the nonlinear adjoint at the predictor: hbar_in[i] += pi_i alpha_bar.
-__global__ __launch_bounds__(256) void k_step_adjoint_post(GroupView g, SynthInput pred,
-                                                           int64_t state_count,
-                                                           double2* hist_bar,
-                                                           const double2* abar) {
-  const int N = g.N;
-  const int m = blockIdx.x, b = blockIdx.z;
-  const int k = blockIdx.y * blockDim.x + threadIdx.x;
-  if (k > N - m) return;
-  const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
-  const double2 a = abar[slot];
-#pragma unroll
-  for (int i = 0; i < kMaxSources; ++i) {
-    if (i < pred.nsrc) {
-      double2 h = hist_bar[(int64_t)i * state_count + slot];
-      h.x += pred.coef[i] * a.x;
-      h.y += pred.coef[i] * a.y;
-      hist_bar[(int64_t)i * state_count + slot] = h;
-    }
-  }
-}
-
-hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, double2* hist_bar,
-                                   double2* nbar, hipStream_t s) {
+hipError_t launch_prep_step_adjoint(const GroupView& g, const AnalOutput& st,
+                                    const SynthInput& pred, double2* hist_bar, hipStream_t s) {
   dim3 grid(g.N + 1, (g.N + 1 + 255) / 256, g.nb);
-  hipLaunchKernelGGL(k_step_adjoint_pre, grid, dim3(256), 0, s, g, st, hist_bar, nbar);
-  return hipGetLastError();
-}
-
-hipError_t launch_step_adjoint_post(const GroupView& g, const SynthInput& pred,
-                                    int64_t state_count, double2* hist_bar, const double2* abar,
-                                    hipStream_t s) {
-  dim3 grid(g.N + 1, (g.N + 1 + 255) / 256, g.nb);
-  hipLaunchKernelGGL(k_step_adjoint_post, grid, dim3(256), 0, s, g, pred, state_count, hist_bar,
-                     abar);
+  hipLaunchKernelGGL(k_prep_step_adjoint, grid, dim3(256), 0, s, g, st, pred, hist_bar);
   return hipGetLastError();
 }
 

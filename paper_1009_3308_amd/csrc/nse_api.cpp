@@ -105,7 +105,6 @@ struct nse_ctx {
   int64_t state_count = 0;
   double2* d_iter = nullptr;
   int* d_flag = nullptr;
-  double2 *d_nbar = nullptr, *d_abar = nullptr;  // adjoint step temporaries, on demand
   std::string err;
   // captured step chunks keyed by (hist, forcing, chunk length)
   std::map<std::tuple<const void*, const void*, int>, GraphEntry> graphs;
@@ -491,8 +490,6 @@ nse_status ensure_adjoint_buffers(nse_ctx* c) {
     NSE_HIP(c, dalloc(&g.d_Fbar, nb * 4 * fs));
     NSE_HIP(c, dalloc(&g.d_Pbar, nb * (size_t)(g.N + 1) * (g.N + 2) * 4));
   }
-  if (!c->d_nbar) NSE_HIP(c, dalloc(&c->d_nbar, (size_t)c->state_count));
-  if (!c->d_abar) NSE_HIP(c, dalloc(&c->d_abar, (size_t)c->state_count));
   return NSE_OK;
 }
 
@@ -679,8 +676,6 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   for (auto& g : ctx->groups) free_group(g);
   (void)hipFree(ctx->d_iter);
   (void)hipFree(ctx->d_flag);
-  (void)hipFree(ctx->d_nbar);
-  (void)hipFree(ctx->d_abar);
   (void)hipFree(ctx->d_hist_save);
   delete ctx;
   return NSE_OK;
@@ -847,13 +842,18 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forc
   }
   pred.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
   double2* hb = (double2*)hist_bar;
-  for (auto& g : ctx->groups)
-    NSE_HIP(ctx, launch_step_adjoint_pre(g.view(), st, hb, ctx->d_nbar, ctx->stream));
-  s = enqueue_nonlinear_adjoint(ctx, pred, ctx->d_nbar, ctx->d_abar);
-  if (s != NSE_OK) return s;
-  for (auto& g : ctx->groups)
-    NSE_HIP(ctx, launch_step_adjoint_post(g.view(), pred, ctx->state_count, hb, ctx->d_abar,
-                                          ctx->stream));
+  SynthInput in = pred;
+  in.adj = hb;  // hbar_out[0]; n_bar is formed inside the five-field synthesis
+  in.adj_step = 1;
+  in.adj_c0 = cc[0];
+  in.adj_h = ctx->params.dt;
+  for (auto& g : ctx->groups) {
+    const GroupView v = g.view();
+    NSE_HIP(ctx, launch_synthesis(v, in, SYNTH_ADJ, ctx->stream));
+    NSE_HIP(ctx, launch_ring_adjoint(v, g.plan, ctx->stream));
+    NSE_HIP(ctx, launch_synthesis_adjoint(v, ctx->stream));
+    NSE_HIP(ctx, launch_prep_step_adjoint(v, st, pred, hb, ctx->stream));
+  }
   return NSE_OK;
 }
 

@@ -93,6 +93,10 @@ struct SynthInput {
   int nsrc;
   double coriolis;  // 2 Omega sqrt(4 pi / 3): absolute-vorticity fold of zeta[1,0]
   const double2* adj;  // SYNTH_ADJ: cotangent n_bar of the nonlinear term (state array)
+  // SYNTH_ADJ inside the step adjoint: adj is hbar_out[0] and
+  // n_bar = -h hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0)
+  int adj_step;
+  double adj_c0, adj_h;
 };
 
 // SYNTH_ADJ: the four forward fields plus a fifth, lambda^(-1/2) n_bar (the
@@ -126,11 +130,8 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
                                hipStream_t s);
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s);
 hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream_t s);
-hipError_t launch_step_adjoint_pre(const GroupView& g, const AnalOutput& st, double2* hist_bar,
-                                   double2* nbar, hipStream_t s);
-hipError_t launch_step_adjoint_post(const GroupView& g, const SynthInput& pred,
-                                    int64_t state_count, double2* hist_bar, const double2* abar,
-                                    hipStream_t s);
+hipError_t launch_prep_step_adjoint(const GroupView& g, const AnalOutput& st,
+                                    const SynthInput& pred, double2* hist_bar, hipStream_t s);
 hipError_t launch_synthesis_mb(const GroupView& g, const SynthInput& in, int B, hipStream_t s);
 hipError_t launch_analysis_mb(const GroupView& g, const AnalOutput& out, int B, hipStream_t s);
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,

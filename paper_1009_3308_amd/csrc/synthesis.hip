@@ -52,13 +52,16 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   __syncthreads();
   build_panel<NF>(pan, a, N, m, L, mode, in.coriolis);
   if (NF == 5) {
-    // fifth field: lambda^(-1/2) n_bar, l = max(m, 1)..N, real at m = 0
+    // fifth field: lambda^(-1/2) n_bar, l = max(m, 1)..N, real at m = 0 (n_bar formed
+    // here from hbar_out[0] inside the step adjoint)
     const double2* nb = in.adj + g.off[b] + coeff_offset(N, m);
     for (int k = threadIdx.x; k < L; k += blockDim.x) {
       const int l = m + k;
       double2 v = make_double2(0.0, 0.0);
       if (l >= 1 && l <= N) {
-        const double r = 1.0 / sqrt((double)l * (l + 1));
+        const double lam = (double)l * (l + 1);
+        double r = 1.0 / sqrt(lam);
+        if (in.adj_step) r *= -in.adj_h / (in.adj_c0 + in.adj_h * g.nu[b] * lam);
         v = make_double2(nb[k].x * r, m == 0 ? 0.0 : nb[k].y * r);
       }
       pan[NF * k + 4] = v;
