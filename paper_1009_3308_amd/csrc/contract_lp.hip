@@ -87,15 +87,61 @@ __device__ __forceinline__ bf16x8 interleave(bf16x4 v, int par) {
 
 }  // namespace
 
-// LDS: alpha coefficients, then the split panel [block][piece][64 lanes] with
-// only the four degrees of the lane's parity stored (bf16x4; the other four of
-// the operand are zero), reused for the 4 x 256 FP64 partial results at the end.
+// LDS: the split panel [block][piece][64 lanes] with only the four degrees of
+// the lane's parity stored (bf16x4; the other four of the operand are zero),
+// reused for the 4 x 256 FP64 partial results at the end.
 size_t synthesis_lp_lds_bytes(int N) {
   const int nblk = (N + 2 + 31) / 32;
   size_t split = (size_t)nblk * 3 * 64 * sizeof(bf16x4);
   const size_t cst = sizeof(double) * kLpWaves * 256;
-  if (split < cst) split = cst;
-  return sizeof(double2) * (size_t)(N + 3) + split;
+  return split > cst ? split : cst;
+}
+
+// LDS of the split-panel kernel: alpha coefficients and the four panels.
+size_t split_panel_lp_lds_bytes(int N) { return sizeof(double2) * (size_t)(5 * N + 11); }
+
+// The split B operand of the synthesis for one (order m, member), computed
+// once per step and shared by every latitude tile: the four coefficient panels
+// of the order are built in LDS (spectral_ops.h), then each 32-degree block is
+// split into three bf16 pieces in operand order: lane column c = l%16 holds
+// (parity c >> 3, field (c & 7) >> 1, re/im c & 1) for K = 8*(l/16) .. +7, of
+// which only the four degrees of the column's parity are stored (bf16x4).
+__global__ __launch_bounds__(kLpThreads) void k_split_panel_lp(GroupView g, SynthInput in,
+                                                               int mode) {
+  const int N = g.N;
+  const int m = blockIdx.x, b = blockIdx.y;
+  const int L = N + 2 - m;
+  const int nblk = (L + 31) / 32;
+  extern __shared__ double2 sh[];
+  double2* a = sh;              // [N + 3]
+  double2* pan = sh + (N + 3);  // [L][4]
+  load_order(a, g, in, b, m, L);
+  __syncthreads();
+  build_panel<4>(pan, a, N, m, L, mode, in.coriolis);
+  __syncthreads();
+  bf16x4* out = reinterpret_cast<bf16x4*>(g.lps + (int64_t)b * g.lpsoff[N + 1] + g.lpsoff[m]);
+  for (int it = threadIdx.x; it < nblk * 64; it += blockDim.x) {
+    const int kb = it >> 6, l = it & 63;
+    const int c = l & 15, q = l >> 4;
+    const int par = c >> 3, fld = (c & 7) >> 1, cmp = c & 1;
+    bf16x4 h[3];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int k = kb * 32 + 8 * q + 2 * jj + par;  // the degrees of this column's parity
+      double v = 0.0;
+      if (k < L) {
+        const double2 P = pan[4 * k + fld];
+        v = cmp ? P.y : P.x;
+      }
+      __bf16 h0, h1, h2;
+      split3(v, h0, h1, h2);
+      h[0][jj] = h0;
+      h[1][jj] = h1;
+      h[2][jj] = h2;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[(kb * 3 + i) * 64 + l] = h[i];
+  }
 }
 
 __global__ __launch_bounds__(kLpThreads) void k_synthesis_lp(GroupView g, SynthInput in, int mode) {
@@ -107,35 +153,12 @@ __global__ __launch_bounds__(kLpThreads) void k_synthesis_lp(GroupView g, SynthI
   const int L = N + 2 - m;
   const int nblk = (L + 31) / 32;
   extern __shared__ double2 sh[];
-  double2* a = sh;                                                // [N + 3]
-  bf16x4* bsplit = reinterpret_cast<bf16x4*>(sh + (N + 3));        // [nblk][3][64]
-  double* cst = reinterpret_cast<double*>(sh + (N + 3));           // reused: [wave][16][16]
-  load_order(a, g, in, b, m, L);
-  __syncthreads();
-  // B operand of every 32-degree block, split once: lane column c = l%16 holds
-  // (parity c >> 3, field (c & 7) >> 1, re/im c & 1) for K = 8*(l/16) .. +7
-  for (int it = threadIdx.x; it < nblk * 64; it += blockDim.x) {
-    const int kb = it >> 6, l = it & 63;
-    const int c = l & 15, q = l >> 4;
-    const int par = c >> 3, fld = (c & 7) >> 1, cmp = c & 1;
-    bf16x4 h[3];
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int k = kb * 32 + 8 * q + 2 * jj + par;  // the degrees of this column's parity
-      double v = 0.0;
-      if (k < L) {
-        const double2 P = panel_value(a, N, m, k, fld, mode, in.coriolis);
-        v = cmp ? P.y : P.x;
-      }
-      __bf16 h0, h1, h2;
-      split3(v, h0, h1, h2);
-      h[0][jj] = h0;
-      h[1][jj] = h1;
-      h[2][jj] = h2;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) bsplit[(kb * 3 + i) * 64 + l] = h[i];
-  }
+  bf16x4* bsplit = reinterpret_cast<bf16x4*>(sh);  // [nblk][3][64]
+  double* cst = reinterpret_cast<double*>(sh);     // reused: [wave][16][16]
+  // the order's split panel (k_split_panel_lp), copied into LDS
+  const bf16x4* src =
+      reinterpret_cast<const bf16x4*>(g.lps + (int64_t)b * g.lpsoff[N + 1] + g.lpsoff[m]);
+  for (int it = threadIdx.x; it < nblk * 3 * 64; it += blockDim.x) bsplit[it] = src[it];
   __syncthreads();
   const int mypar = (threadIdx.x & 15) >> 3;
 
@@ -298,6 +321,9 @@ __global__ __launch_bounds__(kLpThreads) void k_analysis_lp(GroupView g, AnalOut
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
                                hipStream_t s) {
   if (prec != NSE_PREC_BF16X3) return hipErrorInvalidValue;
+  if (!g.lps) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split_panel_lp, dim3(g.N + 1, g.nb), dim3(kLpThreads),
+                     split_panel_lp_lds_bytes(g.N), s, g, in, mode);
   const int ntile = (g.nh + 63) / 64;
   dim3 grid((g.N + 1) * ntile, g.nb);
   hipLaunchKernelGGL(k_synthesis_lp, grid, dim3(kLpThreads), synthesis_lp_lds_bytes(g.N), s, g,

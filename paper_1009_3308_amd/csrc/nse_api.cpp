@@ -33,6 +33,9 @@ struct Group {
   double *d_mu = nullptr, *d_w = nullptr, *d_T1 = nullptr, *d_T2 = nullptr;
   float *d_T1f = nullptr, *d_T2f = nullptr;
   int64_t* d_t2off = nullptr;
+  uint64_t* d_lps = nullptr;      // split-bf16 synthesis panels (BF16X3 groups)
+  int64_t* d_lpsoff = nullptr;
+  int64_t lps_stride = 0;         // per member, 8-byte units
   std::vector<int64_t> t2off;  // [N+2] start of order m in T2
   double2 *d_F = nullptr, *d_W = nullptr, *d_tw = nullptr;
   double2 *d_Fa = nullptr, *d_Fbar = nullptr, *d_Pbar = nullptr;  // adjoint, allocated on demand
@@ -65,6 +68,8 @@ struct Group {
     g.Fbar = d_Fbar;
     g.Pbar = d_Pbar;
     g.W = d_W;
+    g.lps = d_lps;
+    g.lpsoff = d_lpsoff;
     g.tw = d_tw;
     g.off = d_off;
     g.nu = d_nu;
@@ -75,6 +80,7 @@ struct Group {
     GroupView g = view();
     g.nb = 1;
     g.mb_synth = g.mb_anal = 0;
+    if (d_lps) g.lps = d_lps + (int64_t)i * lps_stride;
     g.F = d_F + (int64_t)i * 4 * nlat * (N + 1);
     g.W = d_W + (int64_t)i * nlat * (N + 1);
     if (d_Fa) {
@@ -197,6 +203,8 @@ void free_group(Group& g) {
   (void)hipFree(g.d_T1f);
   (void)hipFree(g.d_T2f);
   (void)hipFree(g.d_t2off);
+  (void)hipFree(g.d_lps);
+  (void)hipFree(g.d_lpsoff);
   (void)hipFree(g.d_F);
   (void)hipFree(g.d_W);
   (void)hipFree(g.d_Fa);
@@ -245,6 +253,15 @@ nse_status build_group(nse_ctx* c, Group& g) {
   if (c->params.precision != NSE_PREC_FP64) {
     NSE_HIP(c, dalloc(&g.d_T1f, ts1));
     NSE_HIP(c, dalloc(&g.d_T2f, ts2));
+  }
+  if (c->params.precision == NSE_PREC_BF16X3) {
+    // per order: ceil(L / 32) blocks x 3 pieces x 64 lanes of 4 bf16
+    std::vector<int64_t> off(g.N + 2, 0);
+    for (int m = 0; m <= g.N; ++m) off[m + 1] = off[m] + (int64_t)((g.N + 2 - m + 31) / 32) * 3 * 64;
+    NSE_HIP(c, dalloc(&g.d_lpsoff, g.N + 2));
+    NSE_HIP(c, hipMemcpy(g.d_lpsoff, off.data(), sizeof(int64_t) * (g.N + 2), hipMemcpyHostToDevice));
+    g.lps_stride = off[g.N + 1];
+    NSE_HIP(c, dalloc(&g.d_lps, (size_t)nb * off[g.N + 1]));
   }
   NSE_HIP(c, dalloc(&g.d_F, (size_t)nb * 4 * g.nlat * (g.N + 1)));
   if (nb >= 2 && g.precision == NSE_PREC_FP64) {
@@ -596,6 +613,7 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
     if (synthesis_lds_bytes(m.N, 5) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
         synthesis_adjoint_lds_bytes((m.nlat + 1) / 2) > 65536 ||
         analysis_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
+        split_panel_lp_lds_bytes(m.N) > 65536 ||
         analysis_lp_lds_bytes((m.nlat + 1) / 2) > 65536) {
       snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,
                m.N);

@@ -75,6 +75,8 @@ struct GroupView {
   double* Pmb;              // batched synthesis: panels [m][k][nbp][8] (rows as T1), or null
   int nbp;                  // member stride of Pmb: nb rounded up to a multiple of 16
   double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
+  uint64_t* lps;            // split-bf16 synthesis panels, 8-byte groups (precision BF16X3)
+  const int64_t* lpsoff;    // [N+2] start of order m in one member's lps (member stride lpsoff[N+1])
   const double2* tw;        // [M] exp(-2 pi i k / M)
   const int64_t* off;       // [nb] complex-slot offset of each member in a state
   const double* nu;         // [nb]
@@ -157,6 +159,7 @@ size_t ring_lds_bytes(int M);
 size_t analysis_lds_bytes(int nh);
 size_t synthesis_adjoint_lds_bytes(int nh);
 size_t synthesis_lp_lds_bytes(int N);
+size_t split_panel_lp_lds_bytes(int N);
 size_t analysis_lp_lds_bytes(int nh);
 
 // Host numerics.
