@@ -94,3 +94,50 @@ def test_t511_trajectory_fields_vs_fp64(prec):
         _say(f"  {label}: rel err u_theta {errs[0]:.3e} u_phi {errs[1]:.3e} zeta {errs[2]:.3e}")
         assert max(errs) < 1e-6
     s64.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_graph_equals_eager_bitwise(prec):
+    N, steps = 127, 37
+    _say(f"case: {prec} graph vs eager N={N}")
+    stream = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(stream):
+        a0, f = pkg.to_device(I.initial_state(N)), pkg.to_device(I.forcing(N))
+        for graph in (False, True):
+            s = pkg.Sphere([(N, 0, 1e-4)], omega=OMEGA, dt=1e-3, precision=prec, graph=graph,
+                           stream=stream)
+            h = s.new_history()
+            h[0] = a0
+            s.step(h, f, 0, steps)
+            s.step(h, f, steps, steps)
+            s.sync()
+            outs.append(h.clone())
+            s.close()
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_members(prec):
+    """Several members (two truncation groups) in one reduced-precision context:
+    each member's nonlinear term within 1e-6 of the FP64 oracle and bitwise equal
+    to the same member alone."""
+    specs = [(63, 0, 1e-4), (31, 0, 1e-3), (63, 0, 5e-4)]
+    _say(f"case: {prec} members {specs}")
+    s = pkg.Sphere(specs, omega=OMEGA, dt=1e-3, precision=prec)
+    a = s.new_state()
+    host = []
+    for i, (N, _, _) in enumerate(specs):
+        host.append(I.member_state(i, N))
+        a[s.member_slice(i)] = pkg.to_device(host[i])
+    got = s.nonlinear(a).cpu().numpy()
+    for i, spec in enumerate(specs):
+        N = spec[0]
+        sl = s.member_slice(i)
+        ref = O.Sphere(N, s.nlat[i]).nonlinear(O.to_tensor(host[i]), OMEGA).numpy()
+        assert rel(got[sl], ref) < 1e-6
+        one = pkg.Sphere([spec], omega=OMEGA, dt=1e-3, precision=prec)
+        assert np.array_equal(one.nonlinear(pkg.to_device(host[i])).cpu().numpy(), got[sl])
+        one.close()
+    s.close()
