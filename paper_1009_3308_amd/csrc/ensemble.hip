@@ -9,15 +9,11 @@
 // Synthesis, per (order m, tile of 64 northern latitudes, member block):
 //   E[lat][c] = sum_{k even} T1[m][k][lat] P[k][c],  O = same over odd k,
 // with the columns c = (member, field, re/im) of the coefficient panels
-// (8 per member; the panels are those of spectral_ops.h, computed first for
-// every member by a small kernel into a panel buffer whose rows follow T1);
-// F(north) = E + O, F(south) = E - O. Both operands of an MFMA come straight
-// from global memory into registers (the table from HBM, the panels from L2),
-// the next two MFMA steps' operands being loaded while the current ones are
-// multiplied; no LDS and no barriers.
-// Two waves per tile, each owning 32 latitudes (two 16-row blocks): its A
-// operands are 16 x 4 blocks of the table (four even or four odd degrees), its
-// B operand a 4 x 16 block of the panels, shared by the two row blocks.
+// (8 per member; the panels of spectral_ops.h, built in LDS 32 degrees at a
+// time from the members' predictor coefficients); F(north) = E + O,
+// F(south) = E - O. Wave w owns latitudes 16w..16w+15 of the tile: its A
+// operand is a 16 x 4 block of the table (four even or four odd degrees), its
+// B operand a 4 x 16 block of the panel chunk in LDS.
 // Analysis, per (order m, tile of 64 degrees, member block):
 //   s[k][c] = sum_p T2[m][k][p] Wf[p][c],  Wf = We (k even) or Wo (k odd),
 // with the columns c = (member, re/im) of the ring spectra folded over
@@ -41,203 +37,6 @@ constexpr int kMbThreads = 256;
 
 __device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// Panels of every member of the group for one order m, written to
-// Pmb[m][k][b][8] (rows k < L = N+2-m in the row order of T1; members past the
-// group are written as zeros): one workgroup per (m, chunk of pm members),
-// the members' predictor coefficients staged in LDS, the pm members of one
-// degree written as one contiguous row piece (pm = 8, or 4 when the staging of
-// eight members would not fit 64 KiB).
-int panel_members(int N) { return (size_t)10 * (N + 4) * sizeof(double2) <= 65536 ? 8 : 4; }
-
-__global__ __launch_bounds__(kMbThreads) void k_panel_mb(GroupView g, SynthInput in, int pm) {
-  extern __shared__ double2 al_dyn[];  // [pm][N + 4]
-  const int N = g.N;
-  const int m = blockIdx.x, b0 = blockIdx.y * pm;
-  const int L = N + 2 - m;
-  auto al = [&](int bb, int kk) -> double2& { return al_dyn[bb * (N + 4) + kk]; };
-  // per-degree coefficients shared by the members: (sqrt(lambda), 1/sqrt(lambda))
-  // at l = m + kk - 1 and (cm, cp) at k = kk
-  double2* sq = al_dyn + pm * (N + 4);  // [L + 2]
-  double2* cc = sq + (N + 4);           // [L]
-  for (int kk = threadIdx.x; kk < L + 2; kk += kMbThreads) {
-    const int ll = m + kk - 1;
-    double2 v = make_double2(0.0, 0.0);
-    if (ll >= m && ll >= 1 && ll <= N) {
-      const double q = sqrt((double)ll * (ll + 1));
-      v = make_double2(q, 1.0 / q);
-    }
-    sq[kk] = v;
-    if (kk < L) {
-      const double dl = (double)(m + kk), dm = (double)m;
-      const double e_l = (kk > 0) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
-      const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
-      cc[kk] = make_double2((dl - 1.0) * e_l, (dl + 2.0) * e_l1);
-    }
-  }
-  const int64_t base = coeff_offset(N, m);
-  for (int i = threadIdx.x; i < pm * (L + 2); i += kMbThreads) {
-    const int bb = i / (L + 2), kk = i - bb * (L + 2);  // al(bb, kk) = alpha[m + kk - 1]
-    const int k = kk - 1, ll = m + k, b = b0 + bb;
-    double2 v = make_double2(0.0, 0.0);
-    if (b < g.nb && k >= 0 && ll >= 1 && ll <= N) {
-      const int64_t slot = g.off[b] + base + k;
-#pragma unroll
-      for (int s = 0; s < kMaxSources; ++s) {
-        if (s < in.nsrc) {
-          const double2 x = in.src[s][slot];
-          v.x += in.coef[s] * x.x;
-          v.y += in.coef[s] * x.y;
-        }
-      }
-      if (m == 0) v.y = 0.0;
-    }
-    al(bb, kk) = v;
-  }
-  __syncthreads();
-  double* P = g.Pmb + (t1_order_offset(N, m, 1) * g.nbp + b0) * 8;
-  for (int i = threadIdx.x; i < pm * L; i += kMbThreads) {
-    const int k = i / pm, bb = i - k * pm;
-    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (b0 + bb < g.nb) {
-      double2 ps[3], zs[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double2 a = al(bb, k + d), q = sq[k + d];
-        ps[d] = make_double2(a.x * q.y, a.y * q.y);
-        zs[d] = make_double2(a.x * q.x, a.y * q.x);
-        if (m == 0 && m + k - 1 + d == 1) zs[d].x += in.coriolis;
-      }
-      const double2 c = cc[k];
-      const double dm = (double)m;
-      v[0] = -dm * ps[1].y;
-      v[1] = dm * ps[1].x;
-      v[2] = c.x * ps[0].x - c.y * ps[2].x;
-      v[3] = c.x * ps[0].y - c.y * ps[2].y;
-      v[4] = c.x * zs[0].x - c.y * zs[2].x;
-      v[5] = c.x * zs[0].y - c.y * zs[2].y;
-      v[6] = -dm * zs[1].y;
-      v[7] = dm * zs[1].x;
-    }
-    double2* row = reinterpret_cast<double2*>(P + ((int64_t)k * g.nbp + bb) * 8);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) row[f] = make_double2(v[2 * f], v[2 * f + 1]);
-  }
-}
-
-// Work items (order m, member block, latitude tile) are taken in XCD-local
-// chunks of one order, so the blocks and tiles of an order share an L2.
-// Two waves per 64-latitude tile, each owning two 16-latitude row blocks, so
-// that every panel operand loaded feeds two MFMAs.
-constexpr int kSynMbThreads = 128;
-
-template <int B>
-__global__ __launch_bounds__(kSynMbThreads) void k_synthesis_mb(GroupView g) {
-  static_assert(B >= 2, "16 or more panel columns");
-  constexpr int NC = 8 * B;                // columns per parity
-  constexpr int NCB = NC / 16;             // 16-column blocks
-  constexpr int NJ = B >= 8 ? 1 : 2;       // MFMA steps (8 degrees each) per pipeline stage
-  constexpr int RB = 2;                    // 16-latitude row blocks per wave
-  const int N = g.N, nh = g.nh, nlat = g.nlat;
-  const int ntile = (nh + 63) / 64;
-  const int nblk = (g.nb + B - 1) / B;
-  const int item = xcd_item(blockIdx.x, ntile * nblk);
-  const int m = item / (ntile * nblk);
-  if (m > N) return;
-  const int rest = item - m * ntile * nblk;
-  const int blk = rest / ntile, tile = rest - blk * ntile;
-  const int L = N + 2 - m;  // degrees m .. N+1
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int arow = lane & 15, kq = lane >> 4;
-  const int lat0 = tile * 64 + wave * 32 + arow;  // this lane's A-operand latitude, row block 0
-  if (tile * 64 + wave * 32 >= nh) return;        // uniform across the wave; no barriers below
-  bool lat_ok[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) lat_ok[rb] = lat0 + 16 * rb < nh;
-  const double* T = g.T1 + t1_order_offset(N, m, nh) + lat0;
-  const int64_t pstride = (int64_t)g.nbp * 8;
-  const double* P = g.Pmb + t1_order_offset(N, m, 1) * pstride + blk * B * 8 + arow;
-
-  doublex4 accE[RB][NCB], accO[RB][NCB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) accE[rb][c] = accO[rb][c] = doublex4{0.0, 0.0, 0.0, 0.0};
-  // operands of one stage: degrees kc + 8 j + 2 kq (even) and +1 (odd)
-  double aE[NJ][RB], aO[NJ][RB], bE[NJ][NCB], bO[NJ][NCB];
-  double nE[NJ][RB], nO[NJ][RB], cE[NJ][NCB], cO[NJ][NCB];
-  auto load = [&](int kc, double (*xE)[RB], double (*xO)[RB], double (*yE)[NCB],
-                  double (*yO)[NCB]) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int kE = kc + 8 * j + 2 * kq, kO = kE + 1;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        xE[j][rb] = (lat_ok[rb] && kE < L) ? T[(int64_t)kE * nh + 16 * rb] : 0.0;
-        xO[j][rb] = (lat_ok[rb] && kO < L) ? T[(int64_t)kO * nh + 16 * rb] : 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        yE[j][c] = (kE < L) ? P[(int64_t)kE * pstride + 16 * c] : 0.0;
-        yO[j][c] = (kO < L) ? P[(int64_t)kO * pstride + 16 * c] : 0.0;
-      }
-    }
-  };
-  load(0, aE, aO, bE, bO);
-  for (int kc = 0; kc < L; kc += 8 * NJ) {
-    const bool more = kc + 8 * NJ < L;
-    if (more) load(kc + 8 * NJ, nE, nO, cE, cO);  // in flight during this stage's products
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          accE[rb][c] = mfma64(aE[j][rb], bE[j][c], accE[rb][c]);
-          accO[rb][c] = mfma64(aO[j][rb], bO[j][c], accO[rb][c]);
-        }
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          aE[j][rb] = nE[j][rb];
-          aO[j][rb] = nO[j][rb];
-        }
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-          bE[j][c] = cE[j][c];
-          bO[j][c] = cO[j][c];
-        }
-      }
-    }
-  }
-
-  // lane holds rows (latitudes) kq + 4r of each row block, column arow of each column block
-  const int b0 = blk * B;
-#pragma unroll
-  for (int c = 0; c < NCB; ++c) {
-    const int col = 16 * c + arow;
-    const int bb = col >> 3, f = (col & 7) >> 1, ri = col & 1;
-    const int b = b0 + bb;
-    if (b >= g.nb) continue;
-    double* out = reinterpret_cast<double*>(g.F + ((int64_t)(b * 4 + f) * (N + 1) + m) * nlat);
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int p = tile * 64 + wave * 32 + 16 * rb + kq + 4 * r;
-        if (p >= nh) continue;
-        const double e = accE[rb][c][r], o = accO[rb][c][r];
-        out[2 * p + ri] = e + o;
-        const int ps = nlat - 1 - p;
-        if (ps != p) out[2 * ps + ri] = e - o;
-      }
-    }
-  }
 }
 
 template <int B>
@@ -345,20 +144,204 @@ __global__ __launch_bounds__(kMbThreads) void k_analysis_mb(GroupView g, AnalOut
   }
 }
 
+// Member-batched synthesis with the panels built in LDS: per (order m,
+// 64-latitude tile, block of B members) four waves of 16 latitudes. The
+// per-degree coefficients of order m (lambda^(+-1/2), cm, cp) are computed
+// once per workgroup; the degree range is taken in chunks of 32: the members'
+// predictor coefficients of a chunk are staged in LDS, the chunk's panels
+// (8 columns per member) are built in LDS, and each wave multiplies its table
+// rows by them on MFMA. The predictor coefficients and table operands of the
+// next chunk are loaded while the current chunk is multiplied.
+constexpr int kChunkS = 32;
+
+template <int B>
+__global__ __launch_bounds__(kMbThreads) void k_synthesis_mb(GroupView g, SynthInput in) {
+  constexpr int NC = 8 * B;            // panel columns per parity
+  constexpr int NCB = NC / 16;         // 16-column blocks
+  constexpr int WP = NC + 2;           // LDS row stride (doubles), padded against bank conflicts
+  constexpr int NA = B * (kChunkS + 2);                        // predictor items per chunk
+  constexpr int NAT = (NA + kMbThreads - 1) / kMbThreads;      // per thread
+  extern __shared__ double lds_s[];
+  const int N = g.N, nh = g.nh, nlat = g.nlat;
+  const int ntile = (nh + 63) / 64;
+  const int nblk = (g.nb + B - 1) / B;
+  const int item = xcd_item(blockIdx.x, ntile * nblk);
+  const int m = item / (ntile * nblk);
+  if (m > N) return;  // uniform across the workgroup
+  const int rest = item - m * ntile * nblk;
+  const int blk = rest / ntile, tile = rest - blk * ntile;
+  const int b0 = blk * B;
+  const int L = N + 2 - m;
+  double* pan = lds_s;                                        // [kChunkS][WP]
+  double2* al = reinterpret_cast<double2*>(pan + kChunkS * WP);  // [B][kChunkS + 2]
+  double2* sq = al + NA;                                      // [N + 4]: (sqrt lam, 1/sqrt lam) at m+kk-1
+  double2* cc = sq + (N + 4);                                 // [N + 2]: (cm, cp) at k
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int arow = lane & 15, kq = lane >> 4;
+  const int lat = tile * 64 + wave * 16 + arow;
+  const bool lat_ok = lat < nh;
+  const double* T = g.T1 + t1_order_offset(N, m, nh) + (lat_ok ? lat : 0);
+  const int64_t base0 = coeff_offset(N, m);
+  const double dm = (double)m;
+
+  for (int kk = threadIdx.x; kk < L + 2; kk += kMbThreads) {
+    const int ll = m + kk - 1;
+    double2 v = make_double2(0.0, 0.0);
+    if (kk >= 1 && ll >= 1 && ll <= N) {
+      const double q = sqrt((double)ll * (ll + 1));
+      v = make_double2(q, 1.0 / q);
+    }
+    sq[kk] = v;
+    if (kk < L) {
+      const double dl = (double)(m + kk);
+      const double e_l = (kk > 0) ? sqrt((dl * dl - dm * dm) / (4.0 * dl * dl - 1.0)) : 0.0;
+      const double e_l1 = sqrt(((dl + 1) * (dl + 1) - dm * dm) / (4.0 * (dl + 1) * (dl + 1) - 1.0));
+      cc[kk] = make_double2((dl - 1.0) * e_l, (dl + 2.0) * e_l1);
+    }
+  }
+  if (NC < WP) {  // padding columns are never read; nothing to clear
+  }
+
+  // predictor coefficients of the chunk starting at kc (degrees kc-1 .. kc+kChunkS)
+  double2 ra[NAT];
+  auto load_alpha = [&](int kc) {
+#pragma unroll
+    for (int j = 0; j < NAT; ++j) {
+      const int i = threadIdx.x + j * kMbThreads;
+      const int bb = i / (kChunkS + 2), kk = i - bb * (kChunkS + 2);
+      const int k = kc - 1 + kk, b = b0 + bb, ll = m + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < NA && b < g.nb && k >= 0 && ll >= 1 && ll <= N) {
+        const int64_t slot = g.off[b] + base0 + k;
+#pragma unroll
+        for (int s = 0; s < kMaxSources; ++s) {
+          if (s < in.nsrc) {
+            const double2 x = in.src[s][slot];
+            v.x += in.coef[s] * x.x;
+            v.y += in.coef[s] * x.y;
+          }
+        }
+        if (m == 0) v.y = 0.0;
+      }
+      ra[j] = v;
+    }
+  };
+  // table operands of a chunk: four MFMA steps of degrees kc + 8 j + 2 kq (+1)
+  double aE[4], aO[4], nE[4], nO[4];
+  auto load_t = [&](int kc, double* xE, double* xO) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kE = kc + 8 * j + 2 * kq, kO = kE + 1;
+      xE[j] = (lat_ok && kE < L) ? T[(int64_t)kE * nh] : 0.0;
+      xO[j] = (lat_ok && kO < L) ? T[(int64_t)kO * nh] : 0.0;
+    }
+  };
+  load_alpha(0);
+  load_t(0, aE, aO);
+
+  doublex4 accE[NCB], accO[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) accE[c] = accO[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  for (int kc = 0; kc < L; kc += kChunkS) {
+    __syncthreads();  // previous chunk's products done: al and pan are free
+#pragma unroll
+    for (int j = 0; j < NAT; ++j) {
+      const int i = threadIdx.x + j * kMbThreads;
+      if (i < NA) al[i] = ra[j];
+    }
+    __syncthreads();
+    // panels of the chunk: item (kk, bb)
+    for (int i = threadIdx.x; i < kChunkS * B; i += kMbThreads) {
+      const int kk = i / B, bb = i - kk * B;
+      const int k = kc + kk;
+      double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (k < L && b0 + bb < g.nb) {
+        double2 ps[3], zs[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double2 a = al[bb * (kChunkS + 2) + kk + d], q = sq[k + d];
+          ps[d] = make_double2(a.x * q.y, a.y * q.y);
+          zs[d] = make_double2(a.x * q.x, a.y * q.x);
+          if (m == 0 && k - 1 + d == 1) zs[d].x += in.coriolis;
+        }
+        const double2 c = cc[k];
+        v[0] = -dm * ps[1].y;
+        v[1] = dm * ps[1].x;
+        v[2] = c.x * ps[0].x - c.y * ps[2].x;
+        v[3] = c.x * ps[0].y - c.y * ps[2].y;
+        v[4] = c.x * zs[0].x - c.y * zs[2].x;
+        v[5] = c.x * zs[0].y - c.y * zs[2].y;
+        v[6] = -dm * zs[1].y;
+        v[7] = dm * zs[1].x;
+      }
+#pragma unroll
+      for (int f = 0; f < 8; ++f) pan[kk * WP + bb * 8 + f] = v[f];
+    }
+    const bool more = kc + kChunkS < L;
+    if (more) {  // next chunk's loads are in flight during this chunk's products
+      load_alpha(kc + kChunkS);
+      load_t(kc + kChunkS, nE, nO);
+    }
+    __syncthreads();
+    const int kend = min(kChunkS, L - kc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (8 * j < kend) {
+        const double* pE = pan + (8 * j + 2 * kq) * WP + arow;
+        const double* pO = pE + WP;
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+          accE[c] = mfma64(aE[j], pE[16 * c], accE[c]);
+          accO[c] = mfma64(aO[j], pO[16 * c], accO[c]);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        aE[j] = nE[j];
+        aO[j] = nO[j];
+      }
+    }
+  }
+
+  // lane holds rows (latitudes) kq + 4r of its wave's 16, column arow of each block
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) {
+    const int col = 16 * c + arow;
+    const int bb = col >> 3, f = (col & 7) >> 1, ri = col & 1;
+    const int b = b0 + bb;
+    if (b >= g.nb) continue;
+    double* out = reinterpret_cast<double*>(g.F + ((int64_t)(b * 4 + f) * (N + 1) + m) * nlat);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = tile * 64 + wave * 16 + kq + 4 * r;
+      if (p >= nh) continue;
+      const double e = accE[c][r], o = accO[c][r];
+      out[2 * p + ri] = e + o;
+      const int ps = nlat - 1 - p;
+      if (ps != p) out[2 * ps + ri] = e - o;
+    }
+  }
+}
+
+size_t synthesis_mb_lds_bytes(int N, int B) {
+  return sizeof(double) * (size_t)kChunkS * (8 * B + 2) +
+         sizeof(double2) * ((size_t)B * (kChunkS + 2) + (size_t)(N + 4) + (size_t)(N + 2));
+}
+
 }  // namespace
 
 hipError_t launch_synthesis_mb(const GroupView& g, const SynthInput& in, int B, hipStream_t s) {
-  if (!g.Pmb) return hipErrorInvalidValue;
-  const int pm = panel_members(g.N);
-  hipLaunchKernelGGL(k_panel_mb, dim3(g.N + 1, g.nbp / pm), dim3(kMbThreads),
-                     sizeof(double2) * (pm + 2) * (g.N + 4), s, g, in, pm);
   const int ntile = (g.nh + 63) / 64;
   const int per_m = ntile * ((g.nb + B - 1) / B);
   dim3 grid(xcd_grid((g.N + 1) * per_m, per_m));
+  const size_t lds = synthesis_mb_lds_bytes(g.N, B);
   switch (B) {
-    case 2: hipLaunchKernelGGL(k_synthesis_mb<2>, grid, dim3(kSynMbThreads), 0, s, g); break;
-    case 4: hipLaunchKernelGGL(k_synthesis_mb<4>, grid, dim3(kSynMbThreads), 0, s, g); break;
-    case 8: hipLaunchKernelGGL(k_synthesis_mb<8>, grid, dim3(kSynMbThreads), 0, s, g); break;
+    case 2: hipLaunchKernelGGL(k_synthesis_mb<2>, grid, dim3(kMbThreads), lds, s, g, in); break;
+    case 4: hipLaunchKernelGGL(k_synthesis_mb<4>, grid, dim3(kMbThreads), lds, s, g, in); break;
+    case 8: hipLaunchKernelGGL(k_synthesis_mb<8>, grid, dim3(kMbThreads), lds, s, g, in); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -39,8 +39,6 @@ struct Group {
   std::vector<int64_t> t2off;  // [N+2] start of order m in T2
   double2 *d_F = nullptr, *d_W = nullptr, *d_tw = nullptr;
   double2 *d_Fa = nullptr, *d_Fbar = nullptr, *d_Pbar = nullptr;  // adjoint, allocated on demand
-  double* d_Pmb = nullptr;  // panels of the member-batched synthesis (FP64 groups of >= 2)
-  int nbp = 0;
   int64_t* d_off = nullptr;
   double* d_nu = nullptr;
 
@@ -62,8 +60,6 @@ struct Group {
     g.T2f = d_T2f;
     g.t2off = d_t2off;
     g.F = d_F;
-    g.Pmb = d_Pmb;
-    g.nbp = nbp;
     g.Fa = d_Fa;
     g.Fbar = d_Fbar;
     g.Pbar = d_Pbar;
@@ -208,7 +204,6 @@ void free_group(Group& g) {
   (void)hipFree(g.d_F);
   (void)hipFree(g.d_W);
   (void)hipFree(g.d_Fa);
-  (void)hipFree(g.d_Pmb);
   (void)hipFree(g.d_Fbar);
   (void)hipFree(g.d_Pbar);
   (void)hipFree(g.d_tw);
@@ -264,10 +259,6 @@ nse_status build_group(nse_ctx* c, Group& g) {
     NSE_HIP(c, dalloc(&g.d_lps, (size_t)nb * off[g.N + 1]));
   }
   NSE_HIP(c, dalloc(&g.d_F, (size_t)nb * 4 * g.nlat * (g.N + 1)));
-  if (nb >= 2 && g.precision == NSE_PREC_FP64) {
-    g.nbp = (nb + 15) / 16 * 16;
-    NSE_HIP(c, dalloc(&g.d_Pmb, (size_t)(ts1 / g.nh) * g.nbp * 8));
-  }
   NSE_HIP(c, dalloc(&g.d_W, (size_t)nb * g.nlat * (g.N + 1)));
   std::vector<double2> tw(g.M);
   const long double two_pi = 6.283185307179586476925286766559005768L;

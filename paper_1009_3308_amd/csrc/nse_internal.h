@@ -72,8 +72,6 @@ struct GroupView {
   double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
   double2* Fbar;            // adjoint: [nb][4][nlat][N+1] cotangents of the field spectra
   double2* Pbar;            // adjoint: [nb][N+1][N+2][4] cotangents of the panels
-  double* Pmb;              // batched synthesis: panels [m][k][nbp][8] (rows as T1), or null
-  int nbp;                  // member stride of Pmb: nb rounded up to a multiple of 16
   double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
   uint64_t* lps;            // split-bf16 synthesis panels, 8-byte groups (precision BF16X3)
   const int64_t* lpsoff;    // [N+2] start of order m in one member's lps (member stride lpsoff[N+1])
