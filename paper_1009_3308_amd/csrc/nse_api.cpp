@@ -104,6 +104,11 @@ struct nse_ctx {
   nse_params params{};
   hipStream_t stream = nullptr;
   std::vector<Group> groups;
+  // streams of groups 1.. (forked from `stream` for each evaluation chain) and
+  // the fork / join events
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
   int64_t state_count = 0;
   double2* d_iter = nullptr;
   int* d_flag = nullptr;
@@ -418,10 +423,45 @@ nse_status autotune_blocks(nse_ctx* c) {
   return st;
 }
 
-// Enqueues one full evaluation chain (synthesis, ring, analysis) for every group.
+// Streams and events for running the chains of several groups side by side.
+nse_status ensure_aux_streams(nse_ctx* c) {
+  const size_t need = c->groups.size() - 1;
+  if (!c->ev_fork) NSE_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  while (c->aux.size() < need) {
+    hipStream_t st = nullptr;
+    NSE_HIP(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    c->aux.push_back(st);
+    hipEvent_t e = nullptr;
+    NSE_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->ev_join.push_back(e);
+  }
+  return NSE_OK;
+}
+
+// Enqueues one full evaluation chain (synthesis, ring, analysis) for every
+// group. The groups are independent: unless kernels are being timed, group 0
+// runs on the context stream and every other group on its own stream forked
+// from it and joined back, so that the chains of different truncations overlap
+// on the GPU (inside a captured graph the fork and the join become edges).
 nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out) {
-  for (auto& g : c->groups) {
+  const bool fork = !c->profiling && c->groups.size() > 1;
+  if (fork) {
+    nse_status s = ensure_aux_streams(c);
+    if (s != NSE_OK) return s;
+    NSE_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+    for (size_t i = 0; i + 1 < c->groups.size(); ++i)
+      NSE_HIP(c, hipStreamWaitEvent(c->aux[i], c->ev_fork, 0));
+  }
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    auto& g = c->groups[gi];
     const GroupView v = g.view();
+    if (fork) {
+      hipStream_t st = gi ? c->aux[gi - 1] : c->stream;
+      NSE_HIP(c, launch_synth_any(v, in, SYNTH_NONLINEAR, st));
+      NSE_HIP(c, launch_ring(v, g.plan, SYNTH_NONLINEAR, nullptr, st));
+      NSE_HIP(c, launch_anal_any(v, out, st));
+      continue;
+    }
     nse_status s;
     s = timed_launch(c, NSE_KERNEL_SYNTHESIS,
                      [&] { return launch_synth_any(v, in, SYNTH_NONLINEAR, c->stream); });
@@ -445,6 +485,12 @@ nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out
       NSE_HIP(c, hipMemcpyAsync(out.hist, c->d_hist_save, hbytes, hipMemcpyDeviceToDevice,
                                 c->stream));
       NSE_HIP(c, launch_anal_any(v, out, c->stream));
+    }
+  }
+  if (fork) {
+    for (size_t i = 0; i + 1 < c->groups.size(); ++i) {
+      NSE_HIP(c, hipEventRecord(c->ev_join[i], c->aux[i]));
+      NSE_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join[i], 0));
     }
   }
   return NSE_OK;
@@ -682,6 +728,9 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto st : ctx->aux) (void)hipStreamDestroy(st);
+  for (auto e : ctx->ev_join) (void)hipEventDestroy(e);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   for (auto& g : ctx->groups) free_group(g);
   (void)hipFree(ctx->d_iter);
   (void)hipFree(ctx->d_flag);
