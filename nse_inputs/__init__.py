@@ -139,6 +139,35 @@ def single_mode(N: int, modes) -> np.ndarray:
     return out
 
 
+def example1_g(t: float, nu: float):
+    """g(t) = nu e^-t (sin 5t + cos 10t) of the manufactured flow of the paper's
+    Example 1, and its derivative."""
+    e = nu * np.exp(-t)
+    s = np.sin(5 * t) + np.cos(10 * t)
+    ds = 5 * np.cos(5 * t) - 10 * np.sin(10 * t)
+    return e * s, e * (ds - s)
+
+
+def example1_state(N0: int, N: int, t: float, nu: float, rate: bool = False) -> np.ndarray:
+    """Coefficients of the manufactured velocity of Example 1,
+    u = t g(t) sum_{L<=N0} [Z_{L,0} + 2 sum_{m>=1} Re Z_{L,m}] + g(t) W1 + (t - 1) g(t) W2,
+    W1 = Z_{1,0} + 2 Re Z_{1,1},  W2 = Z_{2,0} + 2 Re(Z_{2,1} + Z_{2,2}),
+    in the storage of truncation N >= N0 (2 Re Z_{L,m} is the stored coefficient 1
+    at (L, m)); with rate=True the time derivative of those coefficients."""
+    g, dg = example1_g(t, nu)
+    a1 = g + t * dg if rate else t * g                 # coefficient of the sum
+    aw1 = dg if rate else g
+    aw2 = (g + (t - 1) * dg) if rate else (t - 1) * g
+    out = np.zeros(coeff_count(N), dtype=np.complex128)
+    ls, ms = degrees_orders(N)
+    out[(ls >= 1) & (ls <= N0)] = a1
+    for (l, m) in ((1, 0), (1, 1)):
+        out[index(N, l, m)] += aw1
+    for (l, m) in ((2, 0), (2, 1), (2, 2)):
+        out[index(N, l, m)] += aw2
+    return out
+
+
 def as_real_view(alpha: np.ndarray) -> np.ndarray:
     """Interleaved (re, im) float64 view of a complex128 array."""
     return np.ascontiguousarray(alpha).view(np.float64)
