@@ -196,6 +196,99 @@ nse_status nse_analyze_velocity(nse_ctx* ctx, const double* u_grid, double* alph
 nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m,
                                double* out);
 
+/* ---------------------------------------------------------------------------
+ * Adaptive time integration: the NDF_p formulas of eq. (ode_disc) (Section
+ * 4.2; orders 1..5 with the kappa_p printed there), run with variable order and
+ * variable step at a relative error tolerance as in the experiments of
+ * Section 5 (Example 2: orders one to five, tolerance 1e-3). The state is kept
+ * in backward differences D[j] = nabla^j alpha_n at the current step h; an
+ * attempt of order k predicts y0 = sum_{j<=k} D[j] and iterates the corrector
+ *   d = (h (f(t+h) - n(y)) - h nu lambda y0 - sum_{1<=j<=k} gamma_j D[j])
+ *       / ((1 - kappa_k) gamma_k + h nu lambda),   y = y0 + d,
+ * (gamma_j = sum_{i<=j} 1/i; simplified Newton with the diagonal Stokes part
+ * as iteration matrix), with n from the hot path. The local error estimate is
+ * (kappa_k gamma_k + 1/(k+1)) ||d||, ||v|| = max over coefficients of
+ * |v| / max(|alpha_n|, |y|, atol/rtol) (complex modulus, all members of the
+ * context form one system with one step). Control:
+ *  - Newton: at most max_newton sweeps; from the second on, rho = ratio of
+ *    successive correction norms; rho >= 0.9 fails, rho/(1-rho) * norm <=
+ *    0.1 rtol converges (one sweep, max_newton = 1, always converges); a
+ *    failure multiplies h by 0.3;
+ *  - error failure (estimate > rtol): the first in a row multiplies h by
+ *    max(0.1, 0.833 (rtol/err)^(1/(k+1))) or lowers the order if
+ *    min(1, max(0.1, 0.769 (rtol/err_{k-1})^(1/k))) is larger (err_{k-1} from
+ *    nabla^k alpha_{n+1}); the next ones halve h, from the third on at order 1;
+ *  - after k+2 accepted steps at the same h and k, the ratios
+ *    1 / max(0.1, c (err_j/rtol)^(1/(j+1))) of orders j = k (c = 1.2), k-1
+ *    (1.3) and k+1 (1.4, from nabla^{k+2} alpha_{n+1}) are compared; the largest
+ *    (ties: current, then lower order) is taken if it exceeds 1;
+ *  - h <= hmax; a step ending within 10 % of t_end is set to end there; a new
+ *    h rescales D[0..k] to the interpolating polynomial's differences at the
+ *    new spacing;
+ *  - first step: order 1, h = min(hmax, t_end - t0, 0.8 sqrt(rtol)/||F(t0)||)
+ *    unless h0 > 0, D[1] = h F(t0, alpha0), F = f - nu lambda alpha - n.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double rtol;         /* relative tolerance, > 0 (the paper's: 1e-3)      */
+  double atol;         /* absolute tolerance per coefficient, > 0          */
+  double h0;           /* first step (0 = chosen as above)                 */
+  double hmax;         /* largest step (0 = unbounded)                     */
+  int32_t max_order;   /* 1..5                                            */
+  int32_t max_newton;  /* corrector sweeps per attempt, 1..8              */
+} nse_adaptive_params;
+
+/* Called with t before the forcing buffer is read for time t (once per
+ * attempt, with t = t_n + h, and once by nse_adaptive_begin with t0). It may
+ * rewrite the buffer given to nse_adaptive_begin and call the context's other
+ * entry points (not nse_adaptive_*); work it enqueues must be on the context's
+ * stream or complete before it returns. */
+typedef void (*nse_forcing_fn)(void* user, double t);
+
+enum { NSE_ATTEMPT_ACCEPTED = 0, NSE_ATTEMPT_ERROR_FAIL = 1, NSE_ATTEMPT_NEWTON_FAIL = 2 };
+
+typedef struct {
+  double t;            /* start of the attempted step                     */
+  double h;            /* its size                                        */
+  double err;          /* error estimate (NaN after a Newton failure)     */
+  int32_t order;       /* NDF order of the attempt                        */
+  int32_t sweeps;      /* corrector sweeps run                            */
+  int32_t outcome;     /* NSE_ATTEMPT_*                                   */
+  int32_t reserved;
+} nse_adaptive_record;
+
+typedef struct {
+  double t, h;         /* current time and next step                      */
+  int32_t order;       /* next order                                      */
+  int32_t reserved;
+  int64_t accepted, error_failures, newton_failures;
+  int64_t evaluations; /* nonlinear-term evaluations (hot-path chains)    */
+} nse_adaptive_stats;
+
+/* Starts an adaptive integration at (t0, alpha0): alpha0 is a device state of
+ * nse_state_count complex coefficients (copied), `forcing` a device state read
+ * at every attempt (NULL = zero forcing; caller-owned, must stay valid until
+ * the last nse_adaptive_advance), `fn` (may be NULL) refreshes it per time
+ * level. Evaluates F(t0, alpha0) once. Clears the attempt log. NSE_ERR_ARG for
+ * invalid parameters (rtol or atol not > 0, h0 or hmax < 0, max_order outside
+ * 1..5, max_newton outside 1..8) or NULL alpha0. */
+nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
+                              const nse_adaptive_params* params, const double* forcing,
+                              nse_forcing_fn fn, void* user);
+
+/* Integrates to t_end (>= the current time), ending exactly there, and writes
+ * alpha(t_end) to the device state alpha_out (may be NULL); fills *stats if
+ * non-NULL. Waits on the stream once per corrector sweep from the second on
+ * and once per attempt. NSE_ERR_STATE before nse_adaptive_begin or when the
+ * step falls below 16 eps |t|; NSE_ERR_NONFINITE if a norm is NaN/Inf (the
+ * integration cannot continue; call nse_adaptive_begin again). */
+nse_status nse_adaptive_advance(nse_ctx* ctx, double t_end, double* alpha_out,
+                                nse_adaptive_stats* stats);
+
+/* Copies up to `capacity` records of the attempts since nse_adaptive_begin (in
+ * order) to `out` (host) and the total number of attempts to *count. */
+nse_status nse_adaptive_log(const nse_ctx* ctx, nse_adaptive_record* out, int64_t capacity,
+                            int64_t* count);
+
 /* Kernels of the hot path, for per-kernel timing. */
 enum {
   NSE_KERNEL_SYNTHESIS = 0, /* Legendre synthesis of the four grid fields     */

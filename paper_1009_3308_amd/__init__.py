@@ -38,7 +38,10 @@ EXPORTS = (
     "nse_nonlinear_adjoint", "nse_step_adjoint", "nse_synthesize", "nse_legendre_values",
     "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
     "nse_analyze_velocity", "nse_get_member_blocks", "nse_set_member_blocks",
+    "nse_adaptive_begin", "nse_adaptive_advance", "nse_adaptive_log",
 )
+
+ATTEMPT_ACCEPTED, ATTEMPT_ERROR_FAIL, ATTEMPT_NEWTON_FAIL = 0, 1, 2
 
 KERNEL_KINDS = {"synthesis": 0, "ring": 1, "analysis": 2}
 
@@ -58,6 +61,30 @@ class Params(ctypes.Structure):
                 ("newton_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
 
+
+class AdaptiveParams(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("h0", ctypes.c_double),
+                ("hmax", ctypes.c_double), ("max_order", ctypes.c_int32),
+                ("max_newton", ctypes.c_int32)]
+
+
+class AdaptiveRecord(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h", ctypes.c_double), ("err", ctypes.c_double),
+                ("order", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("outcome", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class AdaptiveStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h", ctypes.c_double), ("order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("accepted", ctypes.c_int64),
+                ("error_failures", ctypes.c_int64), ("newton_failures", ctypes.c_int64),
+                ("evaluations", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+FORCING_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_double)
 
 _lib = None
 
@@ -93,6 +120,11 @@ def lib():
         "nse_sync": (st, [vp]),
         "nse_profile_enable": (st, [vp, i32]),
         "nse_profile_read": (st, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
+        "nse_adaptive_begin": (st, [vp, dp, ctypes.c_double, ctypes.POINTER(AdaptiveParams), dp,
+                                    FORCING_FN, vp]),
+        "nse_adaptive_advance": (st, [vp, ctypes.c_double, dp, ctypes.POINTER(AdaptiveStats)]),
+        "nse_adaptive_log": (st, [vp, ctypes.POINTER(AdaptiveRecord), i64,
+                                  ctypes.POINTER(i64)]),
         "nse_status_string": (ctypes.c_char_p, [st]),
         "nse_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -290,6 +322,70 @@ class Sphere:
         _check(lib().nse_legendre_values(self._handle(), member, m, _ptr(out, torch.float64)),
                self._h)
         return out.view(N + 2 - m, nh)
+
+    # -- adaptive integration ------------------------------------------------------
+    def adaptive_begin(self, alpha0, t0: float = 0.0, rtol: float = 1e-3, atol: float = 1e-6,
+                       h0: float = 0.0, hmax: float = 0.0, max_order: int = 5,
+                       max_newton: int = 4, forcing=None):
+        """Starts a variable-order, variable-step NDF integration at (t0, alpha0).
+
+        forcing: None (zero), a state tensor (constant in time), or a callable
+        t -> state tensor, evaluated on the context stream at every time level.
+        """
+        import torch
+        self._ad_error = None
+        fn = FORCING_FN()
+        if callable(forcing):
+            self._ad_fbuf = self.new_state()
+            f = forcing
+
+            def refresh(_user, t):
+                try:
+                    with torch.cuda.stream(self.stream):
+                        self._ad_fbuf.copy_(f(float(t)))
+                except BaseException as e:  # re-raised after the library call returns
+                    if self._ad_error is None:
+                        self._ad_error = e
+
+            fn = FORCING_FN(refresh)
+            fptr = _ptr(self._ad_fbuf, torch.complex128, self.state_count, "forcing")
+        else:
+            self._ad_fbuf = forcing
+            fptr = _ptr(forcing, torch.complex128, self.state_count, "forcing")
+        self._ad_fn = fn  # the library keeps the pointer
+        p = AdaptiveParams(float(rtol), float(atol), float(h0), float(hmax), int(max_order),
+                           int(max_newton))
+        st = lib().nse_adaptive_begin(
+            self._handle(), _ptr(alpha0, torch.complex128, self.state_count, "alpha0"),
+            float(t0), ctypes.byref(p), fptr, fn, None)
+        self._raise_callback_error()
+        _check(st, self._h)
+
+    def _raise_callback_error(self):
+        e, self._ad_error = getattr(self, "_ad_error", None), None
+        if e is not None:
+            raise e
+
+    def adaptive_advance(self, t_end: float, out=None):
+        """Integrates to t_end (exactly); returns (alpha(t_end), stats dict)."""
+        import torch
+        if out is None:
+            out = self.new_state()
+        stats = AdaptiveStats()
+        st = lib().nse_adaptive_advance(
+            self._handle(), float(t_end), _ptr(out, torch.complex128, self.state_count, "alpha_out"),
+            ctypes.byref(stats))
+        self._raise_callback_error()
+        _check(st, self._h)
+        return out, stats.as_dict()
+
+    def adaptive_log(self):
+        """[(t, h, order, sweeps, outcome, err)] of every attempt since adaptive_begin."""
+        n = ctypes.c_int64()
+        _check(lib().nse_adaptive_log(self._handle(), None, 0, ctypes.byref(n)), self._h)
+        buf = (AdaptiveRecord * max(1, n.value))()
+        _check(lib().nse_adaptive_log(self._handle(), buf, n.value, ctypes.byref(n)), self._h)
+        return [(r.t, r.h, r.order, r.sweeps, r.outcome, r.err) for r in buf[:n.value]]
 
     def profile(self, enable: bool = True, repeat: int = 1):
         """Starts (or stops) per-kernel event timing on the context stream; each

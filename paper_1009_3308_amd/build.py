@@ -27,6 +27,7 @@ SOURCES = [
     "contract_lp.hip",
     "adjoint.hip",
     "ensemble.hip",
+    "ndf_adaptive.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -129,6 +129,29 @@ struct nse_ctx {
   std::vector<hipEvent_t> event_pool;
   int64_t prof_count[NSE_KERNEL_KINDS] = {0, 0, 0};
   double prof_ms[NSE_KERNEL_KINDS] = {0, 0, 0};
+  // adaptive NDF integrator: controller state on the host, differences and
+  // sweep buffers on the device
+  struct Adaptive {
+    bool active = false, started = false;
+    nse_adaptive_params p{};
+    const double2* forcing = nullptr;
+    nse_forcing_fn fn = nullptr;
+    void* user = nullptr;
+    double t = 0.0, h = 0.0, fnorm = 0.0;
+    int k = 1, nconst = 0;
+    // work for the next k_ndf_prepare launch: the accepted correction, then a
+    // rescaling of D[0..tk]
+    bool pend_accept = false, pend_transform = false;
+    int pend_k = 0, pend_tk = 0;
+    const double2* pend_d = nullptr;
+    double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1] = {};
+    nse_adaptive_stats stats{};
+    std::vector<nse_adaptive_record> log;
+  } ad;
+  double2* d_ndf = nullptr;  // D [depth][S], then y0, psi, y, dA, dB, n (each S)
+  int ndf_depth = 0;
+  unsigned long long* d_norms = nullptr;
+  unsigned long long* h_norms = nullptr;  // pinned host copy
 };
 
 namespace {
@@ -563,6 +586,303 @@ nse_status enqueue_nonlinear_adjoint(nse_ctx* c, SynthInput in, const double2* n
   return NSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive NDF integrator (host controller).
+
+constexpr int kMaxNewton = 8;
+
+double ndf_gamma(int k) {
+  double g = 0.0;
+  for (int j = 1; j <= k; ++j) g += 1.0 / j;
+  return g;
+}
+// (1 - kappa_k) gamma_k and kappa_k gamma_k + 1/(k+1)
+double ndf_alpha(int k) { return (1.0 - kKappa[k]) * ndf_gamma(k); }
+double ndf_error_constant(int k) { return kKappa[k] * ndf_gamma(k) + 1.0 / (k + 1); }
+
+// Rescaling of backward differences from spacing h to rho h, order k:
+// D_new[j] = sum_i R[j][i] D[i]. The interpolant through y_n .. y_{n-k} is
+// p(t_n + s h) = sum_i c_i(s) D[i], c_i(s) = prod_{q<i} (s + q) / (q + 1)
+// (Newton's backward form); the new differences are
+// nabla'^j = sum_{q<=j} (-1)^q C(j, q) p(t_n - q rho h).
+void step_change(int k, double rho, double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1]) {
+  for (int j = 0; j <= kNdfMaxOrder; ++j)
+    for (int i = 0; i <= kNdfMaxOrder; ++i) R[j][i] = 0.0;
+  for (int j = 0; j <= k; ++j) {
+    for (int i = j; i <= k; ++i) {
+      double acc = 0.0;
+      for (int q = 0; q <= j; ++q) {
+        const double s = -q * rho;
+        double c = 1.0;
+        for (int t = 0; t < i; ++t) c *= (s + t) / (t + 1);
+        acc += ((q & 1) ? -1.0 : 1.0) * binom(j, q) * c;
+      }
+      R[j][i] = acc;
+    }
+  }
+}
+
+nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
+  if (c->d_ndf && c->ndf_depth == depth) return NSE_OK;
+  (void)hipFree(c->d_ndf);
+  c->d_ndf = nullptr;
+  c->ndf_depth = 0;
+  NSE_HIP(c, dalloc(&c->d_ndf, (size_t)(depth + 6) * c->state_count));
+  c->ndf_depth = depth;
+  if (!c->d_norms) {
+    NSE_HIP(c, dalloc(&c->d_norms, 4 * kMaxNewton));
+    NSE_HIP(c, hipHostMalloc((void**)&c->h_norms, sizeof(unsigned long long) * 4 * kMaxNewton,
+                             hipHostMallocDefault));
+  }
+  return NSE_OK;
+}
+
+double2* ndf_buf(nse_ctx* c, int i) {  // 0 y0, 1 psi, 2 y, 3 dA, 4 dB, 5 n
+  return c->d_ndf + (int64_t)(c->ndf_depth + i) * c->state_count;
+}
+
+// Squared norms of sweeps 0..rows-1 to the host (one wait on the stream).
+nse_status read_norms(nse_ctx* c, int rows, double out[][4]) {
+  NSE_HIP(c, hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(unsigned long long) * 4 * rows,
+                            hipMemcpyDeviceToHost, c->stream));
+  NSE_HIP(c, hipStreamSynchronize(c->stream));
+  for (int r = 0; r < rows; ++r)
+    for (int q = 0; q < 4; ++q) {
+      double v;
+      std::memcpy(&v, &c->h_norms[4 * r + q], sizeof(double));
+      out[r][q] = std::sqrt(v);
+    }
+  return NSE_OK;
+}
+
+NdfArgs ndf_args(nse_ctx* c) {
+  NdfArgs a{};
+  a.D = c->d_ndf;
+  a.S = c->state_count;
+  a.depth = c->ndf_depth;
+  a.kmax = c->ad.p.max_order;
+  const double r = c->ad.p.atol / c->ad.p.rtol;
+  a.thr2 = r * r;
+  a.norms = c->d_norms;
+  a.nnorms = 4 * kMaxNewton;
+  return a;
+}
+
+// k_ndf_prepare with the pending accept / rescale and, if `predict`, the
+// predictor of order ad.k; clears the sweep norms.
+nse_status ndf_prepare(nse_ctx* c, bool predict) {
+  auto& ad = c->ad;
+  NdfArgs a = ndf_args(c);
+  a.accept = ad.pend_accept;
+  a.k_acc = ad.pend_k;
+  a.dacc = ad.pend_d;
+  a.transform = ad.pend_transform;
+  a.k = ad.pend_transform ? ad.pend_tk : ad.k;
+  std::memcpy(a.R, ad.R, sizeof(a.R));
+  a.predict = predict;
+  if (predict) a.k = ad.k;
+  for (int j = 0; j <= kNdfMaxOrder; ++j) a.gam[j] = ndf_gamma(j);
+  a.y0 = ndf_buf(c, 0);
+  a.psi = ndf_buf(c, 1);
+  NSE_HIP(c, launch_ndf_prepare(a, c->stream));
+  ad.pend_accept = ad.pend_transform = false;
+  return NSE_OK;
+}
+
+// Changes h (and rescales D[0..k] at the next prepare), composing with a
+// rescaling that is still pending.
+void ndf_rescale(nse_ctx* c, double h_new) {
+  auto& ad = c->ad;
+  double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1];
+  step_change(ad.k, h_new / ad.h, R);
+  if (ad.pend_transform) {
+    double P[kNdfMaxOrder + 1][kNdfMaxOrder + 1] = {};
+    for (int j = 0; j <= ad.k; ++j)
+      for (int i = 0; i <= ad.k; ++i) {
+        double acc = 0.0;
+        for (int t = 0; t <= ad.k; ++t) acc += R[j][t] * ad.R[t][i];
+        P[j][i] = acc;
+      }
+    std::memcpy(ad.R, P, sizeof(P));
+  } else {
+    std::memcpy(ad.R, R, sizeof(R));
+  }
+  ad.pend_transform = true;
+  ad.pend_tk = ad.k;
+  ad.h = h_new;
+  ad.nconst = 0;
+}
+
+// One nonlinear evaluation n(src) into the n buffer.
+nse_status ndf_eval(nse_ctx* c, const double2* src) {
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = src;
+  in.coef[0] = 1.0;
+  in.coriolis = 2.0 * c->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  AnalOutput out{};
+  out.mode = ANAL_NONLINEAR;
+  out.n_out = ndf_buf(c, 5);
+  out.state_count = c->state_count;
+  c->ad.stats.evaluations++;
+  return enqueue_chain(c, in, out);
+}
+
+nse_status ndf_correct(nse_ctx* c, int mode, int sweep, double h, const double2* dprev,
+                       double2* dout) {
+  auto& ad = c->ad;
+  NdfArgs a = ndf_args(c);
+  a.mode = mode;
+  a.k = ad.k;
+  a.n = ndf_buf(c, 5);
+  a.f = ad.forcing;
+  a.y0 = ndf_buf(c, 0);
+  a.psi = ndf_buf(c, 1);
+  a.dprev = dprev;
+  a.dout = dout;
+  a.yout = ndf_buf(c, 2);
+  a.h = h;
+  a.ak = ndf_alpha(ad.k);
+  a.nrow = c->d_norms + 4 * sweep;
+  for (auto& g : c->groups) NSE_HIP(c, launch_ndf_correct(g.view(), a, c->stream));
+  return NSE_OK;
+}
+
+void ndf_record(nse_ctx* c, double t, double h, double err, int k, int sweeps, int outcome) {
+  nse_adaptive_record r{};
+  r.t = t;
+  r.h = h;
+  r.err = err;
+  r.order = k;
+  r.sweeps = sweeps;
+  r.outcome = outcome;
+  c->ad.log.push_back(r);
+}
+
+double ratio_of(double e, double cst, int q, double rtol) {
+  return 1.0 / std::max(0.1, cst * std::pow(e / rtol, 1.0 / (q + 1)));
+}
+
+// One attempt at (t, h, k). Returns NSE_OK with *done_step = true on
+// acceptance.
+nse_status ndf_attempt(nse_ctx* c, bool last, double t_end, int* nfail) {
+  auto& ad = c->ad;
+  const int k = ad.k, K = ad.p.max_newton;
+  const double h = ad.h, t = ad.t, rtol = ad.p.rtol;
+  if (ad.fn) ad.fn(ad.user, t + h);
+  nse_status s = ndf_prepare(c, true);
+  if (s != NSE_OK) return s;
+  double nrm[kMaxNewton][4];
+  double2* dbuf[2] = {ndf_buf(c, 3), ndf_buf(c, 4)};
+  const double2* dprev = nullptr;
+  double2* dcur = nullptr;
+  bool converged = false;
+  int sweeps = 0;
+  double dd_prev = 0.0;
+  for (int i = 1; i <= K; ++i) {
+    sweeps = i;
+    s = ndf_eval(c, i == 1 ? ndf_buf(c, 0) : ndf_buf(c, 2));
+    if (s != NSE_OK) return s;
+    dcur = dbuf[(i - 1) & 1];
+    s = ndf_correct(c, NDF_SWEEP, i - 1, h, dprev, dcur);
+    if (s != NSE_OK) return s;
+    dprev = dcur;
+    if (K == 1) {
+      s = read_norms(c, 1, nrm);
+      if (s != NSE_OK) return s;
+      if (!std::isfinite(nrm[0][0])) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
+      converged = true;
+      break;
+    }
+    if (i == 1) continue;
+    s = read_norms(c, i, nrm);
+    if (s != NSE_OK) return s;
+    if (i == 2) {
+      dd_prev = nrm[0][0];
+      if (!std::isfinite(dd_prev)) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
+    }
+    const double dd = nrm[i - 1][0];
+    if (!std::isfinite(dd)) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
+    if (dd == 0.0) {
+      converged = true;
+      break;
+    }
+    const double rho = dd_prev > 0.0 ? dd / dd_prev : INFINITY;
+    if (rho >= 0.9) break;
+    if (rho / (1.0 - rho) * dd <= 0.1 * rtol) {
+      converged = true;
+      break;
+    }
+    dd_prev = dd;
+  }
+  if (!converged) {
+    ad.stats.newton_failures++;
+    ndf_record(c, t, h, NAN, k, sweeps, NSE_ATTEMPT_NEWTON_FAIL);
+    ndf_rescale(c, 0.3 * h);
+    return NSE_OK;
+  }
+  const double* row = nrm[sweeps - 1];
+  if (!std::isfinite(row[1]) || !std::isfinite(row[2]) || !std::isfinite(row[3]))
+    return fail(c, NSE_ERR_NONFINITE, "non-finite error estimate");
+  const double err = ndf_error_constant(k) * row[1];
+  if (err > rtol) {
+    ad.stats.error_failures++;
+    ndf_record(c, t, h, err, k, sweeps, NSE_ATTEMPT_ERROR_FAIL);
+    ++*nfail;
+    double ratio;
+    if (*nfail == 1) {
+      ratio = std::max(0.1, 0.833 * std::pow(rtol / err, 1.0 / (k + 1)));
+      if (k > 1) {
+        const double ekm1 = ndf_error_constant(k - 1) * row[2];
+        const double rkm1 =
+            ekm1 > 0.0 ? std::min(1.0, std::max(0.1, 0.769 * std::pow(rtol / ekm1, 1.0 / k)))
+                       : 1.0;
+        if (rkm1 > ratio) {
+          ratio = rkm1;
+          ad.k = k - 1;
+        }
+      }
+    } else {
+      ratio = 0.5;
+      if (*nfail >= 3) ad.k = 1;
+    }
+    ndf_rescale(c, ratio * h);
+    return NSE_OK;
+  }
+  // accepted
+  ndf_record(c, t, h, err, k, sweeps, NSE_ATTEMPT_ACCEPTED);
+  ad.stats.accepted++;
+  *nfail = 0;
+  ad.pend_accept = true;
+  ad.pend_k = k;
+  ad.pend_d = dcur;
+  ad.t = last ? t_end : t + h;
+  ad.nconst++;
+  if (ad.nconst >= k + 2) {
+    double r = ratio_of(err, 1.2, k, rtol);
+    int knew = k;
+    if (k > 1) {
+      const double rm = ratio_of(ndf_error_constant(k - 1) * row[2], 1.3, k - 1, rtol);
+      if (rm > r) {
+        r = rm;
+        knew = k - 1;
+      }
+    }
+    if (k < ad.p.max_order) {
+      const double rp = ratio_of(ndf_error_constant(k + 1) * row[3], 1.4, k + 1, rtol);
+      if (rp > r) {
+        r = rp;
+        knew = k + 1;
+      }
+    }
+    if (r > 1.0) {
+      ad.k = knew;
+      ndf_rescale(c, std::min(r * h, ad.p.hmax > 0.0 ? ad.p.hmax : INFINITY));
+    }
+  }
+  return NSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -735,6 +1055,9 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_iter);
   (void)hipFree(ctx->d_flag);
   (void)hipFree(ctx->d_hist_save);
+  (void)hipFree(ctx->d_ndf);
+  (void)hipFree(ctx->d_norms);
+  if (ctx->h_norms) (void)hipHostFree(ctx->h_norms);
   delete ctx;
   return NSE_OK;
 }
@@ -988,6 +1311,121 @@ nse_status nse_profile_read(nse_ctx* ctx, int32_t kind, int64_t* launches, doubl
   if (total_ms) *total_ms = ctx->prof_ms[kind];
   ctx->prof_count[kind] = 0;
   ctx->prof_ms[kind] = 0.0;
+  return NSE_OK;
+}
+
+nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
+                              const nse_adaptive_params* params, const double* forcing,
+                              nse_forcing_fn fn, void* user) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha0 || !params) return fail(ctx, NSE_ERR_ARG, "alpha0 and params must be non-NULL");
+  const nse_adaptive_params& p = *params;
+  if (!(p.rtol > 0.0) || !(p.atol > 0.0) || !std::isfinite(p.rtol) || !std::isfinite(p.atol))
+    return fail(ctx, NSE_ERR_ARG, "rtol and atol must be finite and > 0");
+  if (!(p.h0 >= 0.0) || !(p.hmax >= 0.0))
+    return fail(ctx, NSE_ERR_ARG, "h0 and hmax must be >= 0");
+  if (p.max_order < 1 || p.max_order > kNdfMaxOrder)
+    return fail(ctx, NSE_ERR_ARG, "max_order must be 1..5");
+  if (p.max_newton < 1 || p.max_newton > kMaxNewton)
+    return fail(ctx, NSE_ERR_ARG, "max_newton must be 1..8");
+  if (!std::isfinite(t0)) return fail(ctx, NSE_ERR_ARG, "t0 must be finite");
+  auto& ad = ctx->ad;
+  ad = nse_ctx::Adaptive{};
+  ad.p = p;
+  ad.forcing = (const double2*)forcing;
+  ad.fn = fn;
+  ad.user = user;
+  ad.t = t0;
+  nse_status s = ensure_ndf_buffers(ctx, p.max_order + 3);
+  if (s != NSE_OK) return s;
+  const size_t bytes = sizeof(double2) * (size_t)ctx->state_count;
+  NSE_HIP(ctx, hipMemcpyAsync(ctx->d_ndf, alpha0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  NSE_HIP(ctx, hipMemsetAsync(ctx->d_ndf + ctx->state_count, 0, bytes * (ctx->ndf_depth - 1),
+                              ctx->stream));
+  if (fn) fn(user, t0);
+  s = ndf_prepare(ctx, false);  // clears the norms
+  if (s != NSE_OK) return s;
+  s = ndf_eval(ctx, ctx->d_ndf);
+  if (s != NSE_OK) return s;
+  s = ndf_correct(ctx, NDF_RHS, 0, 0.0, nullptr, ctx->d_ndf + ctx->state_count);
+  if (s != NSE_OK) return s;
+  double nrm[kMaxNewton][4];
+  s = read_norms(ctx, 1, nrm);
+  if (s != NSE_OK) return s;
+  if (!std::isfinite(nrm[0][0])) return fail(ctx, NSE_ERR_NONFINITE, "non-finite F(t0, alpha0)");
+  ad.fnorm = nrm[0][0];
+  ad.active = true;
+  return NSE_OK;
+}
+
+nse_status nse_adaptive_advance(nse_ctx* ctx, double t_end, double* alpha_out,
+                                nse_adaptive_stats* stats) {
+  if (!ctx) return NSE_ERR_ARG;
+  auto& ad = ctx->ad;
+  if (!ad.active) return fail(ctx, NSE_ERR_STATE, "nse_adaptive_begin has not been called");
+  if (!(t_end >= ad.t) || !std::isfinite(t_end))
+    return fail(ctx, NSE_ERR_ARG, "t_end must be finite and >= the current time");
+  const double rtol = ad.p.rtol;
+  const double hmax = ad.p.hmax > 0.0 ? ad.p.hmax : INFINITY;
+  nse_status s = NSE_OK;
+  if (t_end > ad.t && !ad.started) {
+    double h = std::min(hmax, t_end - ad.t);
+    if (ad.p.h0 > 0.0)
+      h = std::min(h, ad.p.h0);
+    else if (ad.fnorm > 0.0 && h * ad.fnorm / (0.8 * std::sqrt(rtol)) > 1.0)
+      h = 0.8 * std::sqrt(rtol) / ad.fnorm;
+    // D[1] holds F(t0, alpha0): scale it to h F
+    ad.pend_transform = true;
+    ad.pend_tk = 1;
+    std::memset(ad.R, 0, sizeof(ad.R));
+    ad.R[0][0] = 1.0;
+    ad.R[1][1] = h;
+    ad.h = h;
+    ad.k = 1;
+    ad.started = true;
+  }
+  int nfail = 0;
+  while (ad.t < t_end) {
+    double h_new = std::min(ad.h, hmax);
+    bool last = false;
+    if (ad.t + 1.1 * h_new >= t_end) {
+      h_new = t_end - ad.t;
+      last = true;
+    }
+    if (h_new != ad.h) ndf_rescale(ctx, h_new);
+    if (ad.h <= 16.0 * 2.220446049250313e-16 * std::fabs(ad.t)) {
+      ad.active = false;
+      return fail(ctx, NSE_ERR_STATE, "step size underflow at t = %.17g", ad.t);
+    }
+    s = ndf_attempt(ctx, last, t_end, &nfail);
+    if (s != NSE_OK) {
+      ad.active = false;
+      return s;
+    }
+  }
+  if (ad.pend_accept || ad.pend_transform) {
+    s = ndf_prepare(ctx, false);
+    if (s != NSE_OK) return s;
+  }
+  if (alpha_out)
+    NSE_HIP(ctx, hipMemcpyAsync(alpha_out, ctx->d_ndf, sizeof(double2) * ctx->state_count,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+  ad.stats.t = ad.t;
+  ad.stats.h = ad.h;
+  ad.stats.order = ad.k;
+  if (stats) *stats = ad.stats;
+  return NSE_OK;
+}
+
+nse_status nse_adaptive_log(const nse_ctx* ctx, nse_adaptive_record* out, int64_t capacity,
+                            int64_t* count) {
+  if (!ctx) return NSE_ERR_ARG;
+  nse_ctx* c = const_cast<nse_ctx*>(ctx);
+  if (capacity < 0 || (capacity > 0 && !out))
+    return fail(c, NSE_ERR_ARG, "out must be non-NULL for capacity > 0");
+  const int64_t n = (int64_t)ctx->ad.log.size();
+  for (int64_t i = 0; i < std::min(n, capacity); ++i) out[i] = ctx->ad.log[i];
+  if (count) *count = n;
   return NSE_OK;
 }
 

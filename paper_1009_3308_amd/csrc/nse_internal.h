@@ -118,6 +118,42 @@ struct AnalOutput {
   int* nonfinite;            // may be null
 };
 
+// Adaptive NDF integrator (Section 4.2, eq. (ode_disc) in backward differences
+// at a quasi-constant step). D[j] = nabla^j y_n at the current spacing h,
+// j = 0..k+2; one attempt predicts y0 = sum_{j<=k} D[j] and
+// psi = sum_{1<=j<=k} gamma_j D[j] and sweeps
+//   d_i = (h (f - n(y_{i-1})) - h nu lambda y0 - psi) / ((1 - kappa_k) gamma_k + h nu lambda),
+//   y_i = y0 + d_i.
+constexpr int kNdfMaxOrder = 5;
+constexpr int kNdfDepth = kNdfMaxOrder + 3;
+enum NdfMode { NDF_SWEEP = 0, NDF_RHS = 1 };
+struct NdfArgs {
+  double2* D;                  // [depth][S]
+  int64_t S;                   // state count (stride of D)
+  int depth;                   // max_order + 3
+  // k_ndf_prepare: accept, then rescale, then predict
+  int accept, k_acc;           // D update with the correction dacc of an order-k_acc step
+  const double2* dacc;
+  int transform, k;            // D[j] <- sum_{i=j..k} R[j][i] D[i], D[k+1..] <- 0
+  double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1];
+  int predict;                 // write y0 and psi for order k
+  double gam[kNdfMaxOrder + 1];  // gamma_j = sum_{i<=j} 1/i
+  double2 *y0, *psi;
+  unsigned long long* norms;   // zeroed by k_ndf_prepare (nnorms entries)
+  int nnorms;
+  // k_ndf_correct
+  int mode;                    // NDF_SWEEP, or NDF_RHS: dout = f - nu lambda D[0] - n
+  int kmax;
+  const double2* n;            // nonlinear term of the previous iterate
+  const double2* f;            // forcing at the new time level (null = 0)
+  const double2* dprev;        // previous correction (null = 0)
+  double2* dout;               // this correction
+  double2* yout;               // this iterate
+  double h, ak, thr2;          // step, (1 - kappa_k) gamma_k, (atol / rtol)^2
+  unsigned long long* nrow;    // squared weighted max norms of this sweep (IEEE bits):
+                               // [0] d - dprev, [1] d, [2] D[k] + d (k > 1), [3] d - D[k+1] (k < kmax)
+};
+
 // Launchers (each enqueues on `s` and returns the launch status).
 hipError_t launch_legendre_table(const GroupView& g, double* T1, double* T2, float* T1f,
                                  float* T2f, hipStream_t s);
@@ -137,6 +173,8 @@ hipError_t launch_analysis_mb(const GroupView& g, const AnalOutput& out, int B, 
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
                                hipStream_t s);
 hipError_t launch_analysis_lp(const GroupView& g, const AnalOutput& out, int prec, hipStream_t s);
+hipError_t launch_ndf_prepare(const NdfArgs& a, hipStream_t s);
+hipError_t launch_ndf_correct(const GroupView& g, const NdfArgs& a, hipStream_t s);
 
 template <typename TT>
 __host__ __device__ inline const TT* synthesis_table(const GroupView& g);
