@@ -243,6 +243,62 @@ def ensemble_timing(pkg, torch, steps=100, warmup=10):
     return out
 
 
+def example2_timing(pkg, torch, T=60.0, N=100, nu=1e-4, omega=1.0, rtol=1e-3):
+    """The paper's Example 2 run: N = 100, nu = 1e-4, Omega = 1, seeded random initial
+    flow (degrees 1..20), forcing f_{3,0}(t), integrated from t = 0 to T with the
+    variable-order (1..5), variable-step NDF integrator at relative tolerance 1e-3
+    (atol 1e-6). Reports the wall time of the whole run and its attempt statistics,
+    beside the cost of one nonlinear evaluation in graph-replayed fixed steps."""
+    import collections
+
+    import nse_inputs as I
+    stream = torch.cuda.Stream()
+    out = {"workload": f"Example 2, N={N}, nu={nu}, Omega={omega}, t=0..{T}, rtol={rtol}"}
+    with torch.cuda.stream(stream):
+        s = pkg.Sphere([(N, 0, nu)], omega=omega, dt=1e-3, order=2, graph=True, stream=stream)
+        F = s.new_state()
+        F[I.index(N, 3, 0)] = 1.0
+        a0 = pkg.to_device(I.example2_state(N, nu))
+        # evaluation cost in fixed graph-replayed steps (one evaluation per step)
+        h = s.new_history()
+        h[0] = a0
+        s.step(h, F, 0, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(h, F, 20, 500)
+        torch.cuda.synchronize()
+        eval_us = 1e6 * (time.perf_counter() - t0) / 500
+        # warm-up of the adaptive path (allocations, first launches)
+        s.adaptive_begin(a0, 0.0, rtol=rtol, atol=1e-6, forcing=(F, I.example2_force))
+        s.adaptive_advance(0.05)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.adaptive_begin(a0, 0.0, rtol=rtol, atol=1e-6, forcing=(F, I.example2_force))
+        a, st = s.adaptive_advance(T)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        log_ = s.adaptive_log()
+        finite = bool(torch.isfinite(torch.view_as_real(a)).all())
+        s.close()
+    orders = collections.Counter(r[2] for r in log_ if r[4] == pkg.ATTEMPT_ACCEPTED)
+    out.update({
+        "wall_s": round(wall, 4),
+        "accepted_steps": st["accepted"],
+        "error_failures": st["error_failures"],
+        "newton_failures": st["newton_failures"],
+        "evaluations": st["evaluations"],
+        "host_waits": st["waits"],
+        "host_wait_s": round(st["wait_seconds"], 4),
+        "mean_sweeps": round(sum(r[3] for r in log_) / max(1, len(log_)), 3),
+        "accepted_orders": {str(k): v for k, v in sorted(orders.items())},
+        "accepted_steps_per_s": round(st["accepted"] / wall, 1),
+        "us_per_evaluation": round(1e6 * wall / st["evaluations"], 2),
+        "fixed_step_us_per_evaluation": round(eval_us, 2),
+        "finite": finite,
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +311,7 @@ def main():
     ap.add_argument("--no-t511", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-example2", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB read + 256 MiB write kernel, the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -357,6 +414,12 @@ def main():
         extra["t255_adjoint_200_steps"] = adj
         extra["t255_adjoint_over_forward"] = adj["ratio"]
         log(f"bench: adjoint {adj}")
+
+    if not args.no_example2:
+        log("bench: Example 2 adaptive run, N=100, t = 0..60")
+        ex2 = example2_timing(pkg, torch)
+        extra["example2_adaptive"] = ex2
+        log(f"bench: example 2 {ex2}")
 
     cpu = None
     if not args.no_cpu_baseline:

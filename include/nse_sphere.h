@@ -237,12 +237,13 @@ typedef struct {
   int32_t max_newton;  /* corrector sweeps per attempt, 1..8              */
 } nse_adaptive_params;
 
-/* Called with t before the forcing buffer is read for time t (once per
- * attempt, with t = t_n + h, and once by nse_adaptive_begin with t0). It may
- * rewrite the buffer given to nse_adaptive_begin and call the context's other
- * entry points (not nse_adaptive_*); work it enqueues must be on the context's
- * stream or complete before it returns. */
-typedef void (*nse_forcing_fn)(void* user, double t);
+/* The forcing at time t is s(t) * forcing, s = fn(user, t) (1 when fn is
+ * NULL). fn is called before the forcing is read for time t (once per attempt,
+ * with t = t_n + h, and once by nse_adaptive_begin with t0). It may also
+ * rewrite the forcing buffer and call the context's other entry points (not
+ * nse_adaptive_*); work it enqueues must be on the context's stream or complete
+ * before it returns. */
+typedef double (*nse_forcing_fn)(void* user, double t);
 
 enum { NSE_ATTEMPT_ACCEPTED = 0, NSE_ATTEMPT_ERROR_FAIL = 1, NSE_ATTEMPT_NEWTON_FAIL = 2 };
 
@@ -262,13 +263,15 @@ typedef struct {
   int32_t reserved;
   int64_t accepted, error_failures, newton_failures;
   int64_t evaluations; /* nonlinear-term evaluations (hot-path chains)    */
+  int64_t waits;       /* host waits for the corrector norms              */
+  double wait_seconds; /* host time spent in those waits                  */
 } nse_adaptive_stats;
 
 /* Starts an adaptive integration at (t0, alpha0): alpha0 is a device state of
  * nse_state_count complex coefficients (copied), `forcing` a device state read
  * at every attempt (NULL = zero forcing; caller-owned, must stay valid until
- * the last nse_adaptive_advance), `fn` (may be NULL) refreshes it per time
- * level. Evaluates F(t0, alpha0) once. Clears the attempt log. NSE_ERR_ARG for
+ * the last nse_adaptive_advance), `fn` (may be NULL) scales or refreshes it per
+ * time level. Evaluates F(t0, alpha0) once. Clears the attempt log. NSE_ERR_ARG for
  * invalid parameters (rtol or atol not > 0, h0 or hmax < 0, max_order outside
  * 1..5, max_newton outside 1..8) or NULL alpha0. */
 nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,

@@ -22,7 +22,7 @@ Z[l,m] = (l(l+1))^(-1/2) Curl Y[l,m] and u = Curl psi.
 Seeds used by the tests and the benchmark:
     1 initial state, 2 forcing (scale 1e-2), 3 target state, 4 finite-difference
     directions, 5 ensemble viscosities, 6 adjoint cotangents (flat spectrum),
-    100+i ensemble member i.
+    7 phases of Example 2's random initial flow, 100+i ensemble member i.
 """
 from __future__ import annotations
 
@@ -166,6 +166,35 @@ def example1_state(N0: int, N: int, t: float, nu: float, rate: bool = False) -> 
     for (l, m) in ((2, 0), (2, 1), (2, 2)):
         out[index(N, l, m)] += aw2
     return out
+
+
+SEED_EXAMPLE2 = 7
+
+
+def example2_state(N: int, nu: float = 1e-4, seed: int = SEED_EXAMPLE2, Lmax: int = 20) -> np.ndarray:
+    """Random initial velocity of the paper's Example 2 in the storage of truncation
+    N >= Lmax: alpha[L,m] = a_L exp(i phi_m) for 1 <= L <= Lmax, 0 <= m <= L, zero
+    above Lmax, with phi_0 = 0, phi_m ~ U(0, 2 pi) for m >= 1 (one phase per order,
+    drawn from numpy.random.default_rng(seed) for m = 1..Lmax), a_L = b_L / |b|,
+    b_L = 2 / (L + (nu L)^2.5)."""
+    if N < Lmax:
+        raise ValueError("N must be >= Lmax")
+    rng = np.random.default_rng(seed)
+    phi = np.concatenate([[0.0], rng.uniform(0.0, 2.0 * np.pi, size=Lmax)])
+    L = np.arange(1, Lmax + 1, dtype=np.float64)
+    b = 2.0 / (L + (nu * L) ** 2.5)
+    a = b / np.linalg.norm(b)
+    out = np.zeros(coeff_count(N), dtype=np.complex128)
+    for l in range(1, Lmax + 1):
+        for m in range(0, l + 1):
+            out[index(N, l, m)] = a[l - 1] * np.exp(1j * phi[m])
+    return out
+
+
+def example2_force(t: float) -> float:
+    """f_{3,0}(t) of Example 2, the only non-zero forcing coefficient: 1 for
+    t <= 10, cos(pi t / 5) exp(-(t - 10) / 5) after."""
+    return 1.0 if t <= 10.0 else float(np.cos(np.pi * t / 5.0) * np.exp(-(t - 10.0) / 5.0))
 
 
 def as_real_view(alpha: np.ndarray) -> np.ndarray:

@@ -1,7 +1,7 @@
 """Variable-order, variable-step NDF integrator: the time discretisation the paper
-uses for its experiments (Section 5: the NDF_p formula (ode_disc) with p = 1..5 and
-the kappa_p listed there; order and step size adapted at a relative error
-tolerance, the step chosen by comparing formulas of neighbouring orders).
+uses for its experiments (Section 4.2: the NDF_p formula (ode_disc) with p = 1..5
+and the kappa_p listed there, the step chosen by comparing formulas of two orders;
+Section 5, Example 2: orders one to five, adaptive steps at a relative tolerance).
 
 TEST INFRASTRUCTURE. Only the test suite, the smoke check and the benchmark's CPU
 baseline leg may import this module. The product path never calls it and shares no

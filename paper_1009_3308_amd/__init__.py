@@ -78,13 +78,14 @@ class AdaptiveStats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("h", ctypes.c_double), ("order", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("accepted", ctypes.c_int64),
                 ("error_failures", ctypes.c_int64), ("newton_failures", ctypes.c_int64),
-                ("evaluations", ctypes.c_int64)]
+                ("evaluations", ctypes.c_int64), ("waits", ctypes.c_int64),
+                ("wait_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
-FORCING_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_double)
+FORCING_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p, ctypes.c_double)
 
 _lib = None
 
@@ -329,25 +330,38 @@ class Sphere:
                        max_newton: int = 4, forcing=None):
         """Starts a variable-order, variable-step NDF integration at (t0, alpha0).
 
-        forcing: None (zero), a state tensor (constant in time), or a callable
-        t -> state tensor, evaluated on the context stream at every time level.
+        forcing: None (zero), a state tensor (constant in time), a callable
+        t -> state tensor (evaluated on the context stream at every time level), or
+        a pair (state tensor F, callable t -> float s) for f(t) = s(t) F.
         """
         import torch
         self._ad_error = None
         fn = FORCING_FN()
-        if callable(forcing):
-            self._ad_fbuf = self.new_state()
-            f = forcing
 
-            def refresh(_user, t):
+        def guarded(body):
+            def cb(_user, t):
                 try:
-                    with torch.cuda.stream(self.stream):
-                        self._ad_fbuf.copy_(f(float(t)))
+                    return body(float(t))
                 except BaseException as e:  # re-raised after the library call returns
                     if self._ad_error is None:
                         self._ad_error = e
+                    return 0.0
+            return FORCING_FN(cb)
 
-            fn = FORCING_FN(refresh)
+        if isinstance(forcing, tuple):
+            self._ad_fbuf, scale = forcing
+            fn = guarded(lambda t: float(scale(t)))
+            fptr = _ptr(self._ad_fbuf, torch.complex128, self.state_count, "forcing")
+        elif callable(forcing):
+            self._ad_fbuf = self.new_state()
+            f = forcing
+
+            def refresh(t):
+                with torch.cuda.stream(self.stream):
+                    self._ad_fbuf.copy_(f(t))
+                return 1.0
+
+            fn = guarded(refresh)
             fptr = _ptr(self._ad_fbuf, torch.complex128, self.state_count, "forcing")
         else:
             self._ad_fbuf = forcing

@@ -109,7 +109,8 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
     const int64_t s = g.off[b] + coeff_offset(N, m) + kk;
     const double Lam = g.nu[b] * ((double)l * (l + 1));
     const double2 n = a.n[s];
-    const double2 f = a.f ? a.f[s] : zero2();
+    double2 f = a.f ? a.f[s] : zero2();
+    f = make_double2(a.fscale * f.x, a.fscale * f.y);
     const double2 D0 = a.D[s];
     if (a.mode == NDF_RHS) {
       double2 F = make_double2(f.x - Lam * D0.x - n.x, f.y - Lam * D0.y - n.y);

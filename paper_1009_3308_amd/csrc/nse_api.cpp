@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -138,6 +139,7 @@ struct nse_ctx {
     nse_forcing_fn fn = nullptr;
     void* user = nullptr;
     double t = 0.0, h = 0.0, fnorm = 0.0;
+    double fscale = 1.0;  // s(t) of the forcing at the level being computed
     int k = 1, nconst = 0;
     // work for the next k_ndf_prepare launch: the accepted correction, then a
     // rescaling of D[0..tk]
@@ -643,9 +645,13 @@ double2* ndf_buf(nse_ctx* c, int i) {  // 0 y0, 1 psi, 2 y, 3 dA, 4 dB, 5 n
 
 // Squared norms of sweeps 0..rows-1 to the host (one wait on the stream).
 nse_status read_norms(nse_ctx* c, int rows, double out[][4]) {
+  const auto t0 = std::chrono::steady_clock::now();
   NSE_HIP(c, hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(unsigned long long) * 4 * rows,
                             hipMemcpyDeviceToHost, c->stream));
   NSE_HIP(c, hipStreamSynchronize(c->stream));
+  c->ad.stats.waits++;
+  c->ad.stats.wait_seconds +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int r = 0; r < rows; ++r)
     for (int q = 0; q < 4; ++q) {
       double v;
@@ -736,6 +742,7 @@ nse_status ndf_correct(nse_ctx* c, int mode, int sweep, double h, const double2*
   a.k = ad.k;
   a.n = ndf_buf(c, 5);
   a.f = ad.forcing;
+  a.fscale = ad.fscale;
   a.y0 = ndf_buf(c, 0);
   a.psi = ndf_buf(c, 1);
   a.dprev = dprev;
@@ -769,7 +776,7 @@ nse_status ndf_attempt(nse_ctx* c, bool last, double t_end, int* nfail) {
   auto& ad = c->ad;
   const int k = ad.k, K = ad.p.max_newton;
   const double h = ad.h, t = ad.t, rtol = ad.p.rtol;
-  if (ad.fn) ad.fn(ad.user, t + h);
+  ad.fscale = ad.fn ? ad.fn(ad.user, t + h) : 1.0;
   nse_status s = ndf_prepare(c, true);
   if (s != NSE_OK) return s;
   double nrm[kMaxNewton][4];
@@ -1342,7 +1349,7 @@ nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
   NSE_HIP(ctx, hipMemcpyAsync(ctx->d_ndf, alpha0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   NSE_HIP(ctx, hipMemsetAsync(ctx->d_ndf + ctx->state_count, 0, bytes * (ctx->ndf_depth - 1),
                               ctx->stream));
-  if (fn) fn(user, t0);
+  ad.fscale = fn ? fn(user, t0) : 1.0;
   s = ndf_prepare(ctx, false);  // clears the norms
   if (s != NSE_OK) return s;
   s = ndf_eval(ctx, ctx->d_ndf);

@@ -145,7 +145,8 @@ struct NdfArgs {
   int mode;                    // NDF_SWEEP, or NDF_RHS: dout = f - nu lambda D[0] - n
   int kmax;
   const double2* n;            // nonlinear term of the previous iterate
-  const double2* f;            // forcing at the new time level (null = 0)
+  const double2* f;            // forcing buffer (null = 0), scaled by fscale
+  double fscale;
   const double2* dprev;        // previous correction (null = 0)
   double2* dout;               // this correction
   double2* yout;               // this iterate

@@ -231,3 +231,43 @@ def test_adaptive_hmax_and_h0():
     o = integ.advance(1.0)
     _compare_logs(glog, integ.log, "hmax")
     assert float((out.cpu() - o).abs().max()) <= 1e-10 * float(o.abs().max())
+
+
+def test_adaptive_example2_matches_oracle():
+    # the paper's Example 2 setting (N = 100, nu = 1e-4, Omega = 1, random initial
+    # flow of degrees 1..20, forcing f_{3,0}) over a short interval
+    N, nu, omega, T = 100, 1e-4, 1.0, 0.08
+    _say(f"case adaptive example 2 N={N} T={T}")
+    a0 = I.example2_state(N, nu)
+    s = pkg.Sphere([(N, 0, nu)], omega=omega, dt=1e-3, order=2)
+    F = s.new_state()
+    F[I.index(N, 3, 0)] = 1.0
+    s.adaptive_begin(pkg.to_device(a0), 0.0, forcing=(F, I.example2_force))
+    out, stats = s.adaptive_advance(T)
+    glog = s.adaptive_log()
+    g = out.cpu()
+    s.close()
+    Fo = torch.zeros(O.coeff_count(N), dtype=torch.complex128)
+    Fo[I.index(N, 3, 0)] = 1.0
+    integ = _oracle_integrator(N, [nu], lambda t: Fo * I.example2_force(t), omega=omega)
+    integ.begin(O.to_tensor(a0), 0.0)
+    o = integ.advance(T)
+    _say(f"  attempts {len(glog)} sweeps {sum(r[3] for r in glog)}")
+    _compare_logs(glog, integ.log, "example2")
+    assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
+
+
+def test_adaptive_forcing_callback_error_propagates():
+    N = 15
+    s = pkg.Sphere([(N, 0, 1e-3)], omega=OMEGA, dt=1e-3, order=2)
+    F = pkg.to_device(I.forcing(N))
+
+    def scale(t):
+        if t > 0.3:
+            raise ZeroDivisionError("forcing undefined")
+        return 1.0
+
+    s.adaptive_begin(pkg.to_device(I.initial_state(N)), 0.0, forcing=(F, scale))
+    with pytest.raises(ZeroDivisionError):
+        s.adaptive_advance(1.0)
+    s.close()

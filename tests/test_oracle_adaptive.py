@@ -5,6 +5,8 @@ polynomial samples, the NDF_p formula (ode_disc) solved directly over values,
 closed-form solutions of linear and nonlinear test equations.
 """
 import math
+
+import numpy as np
 from fractions import Fraction
 
 import pytest
@@ -164,3 +166,28 @@ def test_rejections_recover():
     outcomes = [rec[4] for rec in integ.log]
     assert A.ERROR_FAIL in outcomes
     assert integ.t == 2.0
+
+
+def test_example2_inputs():
+    import nse_inputs as I
+    N, nu = 30, 1e-4
+    a = I.example2_state(N, nu)
+    ls, ms = I.degrees_orders(N)
+    L = np.arange(1, 21, dtype=np.float64)
+    b = 2.0 / (L + (nu * L) ** 2.5)
+    aL = b / np.linalg.norm(b)
+    for l in range(1, N + 1):
+        sel = ls == l
+        if l <= 20:
+            assert np.allclose(np.abs(a[sel]), aL[l - 1], rtol=1e-15, atol=0)
+        else:
+            assert not a[sel].any()
+    assert not a[ls == 0].any()
+    assert np.all(a[ms == 0].imag == 0)
+    assert abs(np.sum(aL ** 2) - 1.0) < 1e-15
+    # one phase per order, shared by every degree
+    for m in range(1, 21):
+        ph = np.angle(a[(ms == m) & (ls <= 20)])
+        assert np.allclose(ph, ph[0], atol=1e-12)
+    assert I.example2_force(10.0) == 1.0
+    assert abs(I.example2_force(15.0) - math.cos(3 * math.pi) * math.exp(-1.0)) < 1e-15
