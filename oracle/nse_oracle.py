@@ -412,6 +412,52 @@ class Stepper:
 
 
 # ---------------------------------------------------------------------------
+# Diagnostics of the experiments (Section 5.2 and 5.3).
+# ---------------------------------------------------------------------------
+
+
+def energy_spectrum(alpha: torch.Tensor, N: int) -> torch.Tensor:
+    """E(L) = sum_{|m| <= L} |alpha[L,m]|^2 for L = 0..N (energy); the stored m > 0
+    coefficient stands for m and -m."""
+    w = torch.where(orders(N) > 0, 2.0, 1.0).to(F64)
+    E = torch.zeros(N + 1, dtype=F64)
+    E.index_add_(0, degrees(N).long(), w * alpha.abs() ** 2)
+    return E
+
+
+def stream_function_psi(sphere: "Sphere", alpha: torch.Tensor) -> torch.Tensor:
+    """Psi_N = -sum lambda^(-1/2) alpha[L,m] Y[L,m] on the grid (eq:vort_app)."""
+    return -sphere.stream_function(alpha)
+
+
+def embed(alpha: torch.Tensor, n_src: int, n_dst: int, lmax: int) -> torch.Tensor:
+    """The coefficients of degree <= lmax of a truncation-n_src state, stored in
+    truncation n_dst (zero elsewhere): the orthogonal projection P_lmax."""
+    out = torch.zeros(coeff_count(n_dst), dtype=C128)
+    for m in range(min(n_src, n_dst, lmax) + 1):
+        for l in range(m, min(n_src, n_dst, lmax) + 1):
+            out[m_offset(n_dst, m) + l - m] = alpha[m_offset(n_src, m) + l - m]
+    return out
+
+
+def inertial_manifold(sphere: "Sphere", alpha: torch.Tensor, n_src: int, N1: int,
+                      forcing, nu: float, omega: float) -> torch.Tensor:
+    """Phi = (nu A + C)^(-1) (P_N' - P_N1) [f - B(u1, u1)], u1 = P_N1 u (eq:p-p),
+    N' = sphere.N. B is the advection term alone (the Coriolis part is the C of the
+    inverse); (nu A + C) is diagonal on Z[L,m]: nu lambda_L - 2 i Omega m / lambda_L
+    ((stok_eig), (Coriolis_ZLm))."""
+    N = sphere.N
+    u1 = embed(alpha, n_src, N, N1)
+    b = sphere.nonlinear(u1, 0.0)
+    r = -b if forcing is None else forcing - b
+    lam = sphere.lam.clone()
+    lam[0] = 1.0
+    diag = nu * lam - 2j * omega * orders(N) / lam
+    band = degrees(N) > N1
+    return clean(torch.where(band, r / diag, torch.zeros_like(r)), N)
+
+
+# ---------------------------------------------------------------------------
 # Misfit of the final state.
 # ---------------------------------------------------------------------------
 
