@@ -197,6 +197,36 @@ nse_status nse_legendre_values(nse_ctx* ctx, int32_t member, int32_t m,
                                double* out);
 
 /* ---------------------------------------------------------------------------
+ * Diagnostics of the experiments (Section 5.3).
+ * ------------------------------------------------------------------------- */
+
+/* Energy spectrum of every member (eq. (energy)): E(L) = sum_{|m|<=L}
+ * |alpha[L,m]|^2 for L = 0..N (the stored m > 0 coefficient counts for m and
+ * -m). alpha: device state; E_out: device doubles [member][N_member + 1],
+ * members in order. */
+nse_status nse_energy_spectrum(nse_ctx* ctx, const double* alpha, double* E_out);
+
+/* As nse_synthesize, with the vorticity stream function of eq. (eq:vort_app),
+ * Psi_N = -sum lambda^(-1/2) alpha[L,m] Y[L,m] (so that the vorticity is
+ * xhat Delta Psi_N), in place of the vorticity: grid_out holds u_theta, u_phi,
+ * Psi_N per member. */
+nse_status nse_synthesize_psi(nse_ctx* ctx, const double* alpha, double* grid_out);
+
+/* Approximate inertial manifold (eq. (eq:p-p)): for every member (truncation
+ * N', viscosity nu > 0; Omega of the context)
+ *   phi = (nu A + C)^(-1) (P_N' - P_N1) [f - B(u1, u1)],  u1 = P_N1 u,
+ * with B the advection term alone, evaluated by the hot path on the member's
+ * grid (exact for u1 of degree N1 <= N'), and (nu A + C) diagonal on Z[L,m]:
+ * nu lambda_L - 2 i Omega m / lambda_L (eqs. (stok_eig), (Coriolis_ZLm)). The
+ * paper takes N' = 2 N1. alpha_src: device coefficients of u stored at
+ * truncation n_src, [member][(n_src+1)(n_src+2)/2]; only degrees <= N1 are read.
+ * forcing: device state of the context (NULL = 0). phi_out: device state of the
+ * context, zero at degrees <= N1. NSE_ERR_ARG for N1 outside 1..n_src or above
+ * a member's N, nu <= 0, or phi_out aliasing an input. */
+nse_status nse_inertial_manifold(nse_ctx* ctx, const double* alpha_src, int32_t n_src,
+                                 int32_t N1, const double* forcing, double* phi_out);
+
+/* ---------------------------------------------------------------------------
  * Adaptive time integration: the NDF_p formulas of eq. (ode_disc) (Section
  * 4.2; orders 1..5 with the kappa_p printed there), run with variable order and
  * variable step at a relative error tolerance as in the experiments of

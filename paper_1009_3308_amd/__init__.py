@@ -39,6 +39,7 @@ EXPORTS = (
     "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
     "nse_analyze_velocity", "nse_get_member_blocks", "nse_set_member_blocks",
     "nse_adaptive_begin", "nse_adaptive_advance", "nse_adaptive_log",
+    "nse_energy_spectrum", "nse_synthesize_psi", "nse_inertial_manifold",
 )
 
 ATTEMPT_ACCEPTED, ATTEMPT_ERROR_FAIL, ATTEMPT_NEWTON_FAIL = 0, 1, 2
@@ -126,6 +127,9 @@ def lib():
         "nse_adaptive_advance": (st, [vp, ctypes.c_double, dp, ctypes.POINTER(AdaptiveStats)]),
         "nse_adaptive_log": (st, [vp, ctypes.POINTER(AdaptiveRecord), i64,
                                   ctypes.POINTER(i64)]),
+        "nse_energy_spectrum": (st, [vp, dp, dp]),
+        "nse_synthesize_psi": (st, [vp, dp, dp]),
+        "nse_inertial_manifold": (st, [vp, dp, i32, i32, dp, dp]),
         "nse_status_string": (ctypes.c_char_p, [st]),
         "nse_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -323,6 +327,45 @@ class Sphere:
         _check(lib().nse_legendre_values(self._handle(), member, m, _ptr(out, torch.float64)),
                self._h)
         return out.view(N + 2 - m, nh)
+
+    # -- diagnostics (Section 5.3) -----------------------------------------------
+    def energy_spectrum(self, alpha, out=None):
+        """E(L), L = 0..N, of every member: float64 [sum over members of N+1]."""
+        import torch
+        n = sum(spec[0] + 1 for spec in self.member_specs)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().nse_energy_spectrum(
+            self._handle(), _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+            _ptr(out, torch.float64, n, "E_out")), self._h)
+        return out
+
+    def synthesize_psi(self, alpha):
+        """[(u_theta, u_phi, Psi_N) per member] on the grid (Psi_N of eq. (eq:vort_app))."""
+        import torch
+        sizes = [3 * nl * 2 * nl for nl in self.nlat]
+        out = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+        _check(lib().nse_synthesize_psi(
+            self._handle(), _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+            _ptr(out, torch.float64, None, "grid_out")), self._h)
+        res, off = [], 0
+        for nl, sz in zip(self.nlat, sizes):
+            res.append(out[off:off + sz].view(3, nl, 2 * nl))
+            off += sz
+        return res
+
+    def inertial_manifold(self, alpha_src, n_src: int, N1: int, forcing=None, out=None):
+        """phi = (nu A + C)^-1 (P_N' - P_N1)[f - B(u1, u1)], u1 = P_N1 u (eq. (eq:p-p));
+        alpha_src holds every member at truncation n_src."""
+        import torch
+        if out is None:
+            out = self.new_state()
+        nsrc = len(self.member_specs) * coeff_count(n_src)
+        _check(lib().nse_inertial_manifold(
+            self._handle(), _ptr(alpha_src, torch.complex128, nsrc, "alpha_src"), int(n_src),
+            int(N1), _ptr(forcing, torch.complex128, self.state_count, "forcing"),
+            _ptr(out, torch.complex128, self.state_count, "phi_out")), self._h)
+        return out
 
     # -- adaptive integration ------------------------------------------------------
     def adaptive_begin(self, alpha0, t0: float = 0.0, rtol: float = 1e-3, atol: float = 1e-6,

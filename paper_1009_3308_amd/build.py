@@ -28,6 +28,7 @@ SOURCES = [
     "adjoint.hip",
     "ensemble.hip",
     "ndf_adaptive.hip",
+    "diagnostics.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kLpThreads) void k_split_panel_lp(GroupView g, Synt
   double2* pan = sh + (N + 3);  // [L][4]
   load_order(a, g, in, b, m, L);
   __syncthreads();
-  build_panel<4>(pan, a, N, m, L, mode, in.coriolis);
+  build_panel<4>(pan, a, N, m, L, mode, in.coriolis, in.stream != 0);
   __syncthreads();
   bf16x4* out = reinterpret_cast<bf16x4*>(g.lps + (int64_t)b * g.lpsoff[N + 1] + g.lpsoff[m]);
   for (int it = threadIdx.x; it < nblk * 64; it += blockDim.x) {

@@ -150,6 +150,7 @@ struct nse_ctx {
     nse_adaptive_stats stats{};
     std::vector<nse_adaptive_record> log;
   } ad;
+  double2* d_diag = nullptr;  // inertial manifold: band-limited input, its nonlinear term
   double2* d_ndf = nullptr;  // D [depth][S], then y0, psi, y, dA, dB, n (each S)
   int ndf_depth = 0;
   unsigned long long* d_norms = nullptr;
@@ -1063,6 +1064,7 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_flag);
   (void)hipFree(ctx->d_hist_save);
   (void)hipFree(ctx->d_ndf);
+  (void)hipFree(ctx->d_diag);
   (void)hipFree(ctx->d_norms);
   if (ctx->h_norms) (void)hipHostFree(ctx->h_norms);
   delete ctx;
@@ -1318,6 +1320,83 @@ nse_status nse_profile_read(nse_ctx* ctx, int32_t kind, int64_t* launches, doubl
   if (total_ms) *total_ms = ctx->prof_ms[kind];
   ctx->prof_count[kind] = 0;
   ctx->prof_ms[kind] = 0.0;
+  return NSE_OK;
+}
+
+nse_status nse_energy_spectrum(nse_ctx* ctx, const double* alpha, double* E_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !E_out) return fail(ctx, NSE_ERR_ARG, "alpha and E_out must be non-NULL");
+  int64_t eoff = 0;
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_energy_spectrum(v, (const double2*)alpha, E_out + eoff, ctx->stream));
+    eoff += g.N + 1;
+  }
+  return NSE_OK;
+}
+
+nse_status nse_synthesize_psi(nse_ctx* ctx, const double* alpha, double* grid_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !grid_out) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = (const double2*)alpha;
+  in.coef[0] = 1.0;
+  in.stream = 1;
+  int64_t goff = 0;
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_synth_any(v, in, SYNTH_GRID, ctx->stream));
+    NSE_HIP(ctx, launch_ring(v, g.plan, SYNTH_GRID, grid_out + goff, ctx->stream));
+    goff += (int64_t)3 * g.nlat * g.M;
+  }
+  return NSE_OK;
+}
+
+nse_status nse_inertial_manifold(nse_ctx* ctx, const double* alpha_src, int32_t n_src,
+                                 int32_t N1, const double* forcing, double* phi_out) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha_src || !phi_out) return fail(ctx, NSE_ERR_ARG, "alpha_src and phi_out must be non-NULL");
+  if (n_src < 1) return fail(ctx, NSE_ERR_ARG, "n_src must be >= 1");
+  if (N1 < 1 || N1 > n_src) return fail(ctx, NSE_ERR_ARG, "N1 must be in 1..n_src");
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    if (N1 > ctx->members[i].N)
+      return fail(ctx, NSE_ERR_ARG, "N1 exceeds the truncation of member %zu", i);
+    if (!(ctx->members[i].nu > 0.0))
+      return fail(ctx, NSE_ERR_ARG, "nu of member %zu must be > 0 ((nu A + C) is inverted)", i);
+  }
+  if ((const void*)phi_out == (const void*)alpha_src || (const void*)phi_out == (const void*)forcing)
+    return fail(ctx, NSE_ERR_ARG, "phi_out may not alias the inputs");
+  if (!ctx->d_diag) NSE_HIP(ctx, dalloc(&ctx->d_diag, 2 * (size_t)ctx->state_count));
+  double2* band = ctx->d_diag;
+  double2* nl = ctx->d_diag + ctx->state_count;
+  const int64_t src_stride = nse_coeff_count(n_src);
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_band_input(v, (const double2*)alpha_src + (int64_t)i * src_stride, n_src,
+                                   N1, band, ctx->stream));
+  }
+  // B(u1, u1) alone: the Coriolis part belongs to the inverted operator
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = band;
+  in.coef[0] = 1.0;
+  in.coriolis = 0.0;
+  AnalOutput out{};
+  out.mode = ANAL_NONLINEAR;
+  out.n_out = nl;
+  out.state_count = ctx->state_count;
+  nse_status s = enqueue_chain(ctx, in, out);
+  if (s != NSE_OK) return s;
+  for (size_t i = 0; i < ctx->members.size(); ++i) {
+    const Group& g = ctx->groups[ctx->member_group[i]];
+    const GroupView v = g.member_view(ctx->member_index[i]);
+    NSE_HIP(ctx, launch_inertial_manifold(v, nl, (const double2*)forcing, N1, ctx->params.omega,
+                                          (double2*)phi_out, ctx->stream));
+  }
   return NSE_OK;
 }
 

@@ -97,6 +97,7 @@ struct SynthInput {
   // n_bar = -h hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0)
   int adj_step;
   double adj_c0, adj_h;
+  int stream;  // SYNTH_GRID: third field Psi_N = -sum lambda^(-1/2) alpha Y instead of zeta
 };
 
 // SYNTH_ADJ: the four forward fields plus a fifth, lambda^(-1/2) n_bar (the
@@ -175,6 +176,14 @@ hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mod
                                hipStream_t s);
 hipError_t launch_analysis_lp(const GroupView& g, const AnalOutput& out, int prec, hipStream_t s);
 hipError_t launch_ndf_prepare(const NdfArgs& a, hipStream_t s);
+// Diagnostics (Section 5.3): energy spectrum E[b][L], band-limited copy of a
+// state stored at truncation n_src, approximate inertial manifold.
+hipError_t launch_energy_spectrum(const GroupView& g, const double2* alpha, double* E,
+                                  hipStream_t s);
+hipError_t launch_band_input(const GroupView& g, const double2* src, int n_src, int lmax,
+                             double2* dst, hipStream_t s);
+hipError_t launch_inertial_manifold(const GroupView& g, const double2* n, const double2* f,
+                                    int N1, double omega, double2* phi, hipStream_t s);
 hipError_t launch_ndf_correct(const GroupView& g, const NdfArgs& a, hipStream_t s);
 
 template <typename TT>

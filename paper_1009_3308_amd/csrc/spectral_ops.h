@@ -70,10 +70,12 @@ __device__ inline double2 panel_value(const double2* a, int N, int m, int k, int
 }
 
 // All four panels of order m into pan[NF k + f], k < L (one degree per thread,
-// the neighbouring coefficients shared by the four fields).
+// the neighbouring coefficients shared by the four fields). With `stream` set,
+// the grid-output mode puts the stream function -lambda^(-1/2) alpha (Psi_N of
+// eq. (eq:vort_app)) in f2 instead of the vorticity.
 template <int NF = 4>
 __device__ inline void build_panel(double2* pan, const double2* a, int N, int m, int L, int mode,
-                                   double coriolis) {
+                                   double coriolis, bool stream = false) {
   const double dm = (double)m;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     const int l = m + k;
@@ -100,7 +102,7 @@ __device__ inline void build_panel(double2* pan, const double2* a, int N, int m,
       pan[NF * k + 2] = make_double2(cm * zs[0].x - cp * zs[2].x, cm * zs[0].y - cp * zs[2].y);
       pan[NF * k + 3] = make_double2(-dm * zs[1].y, dm * zs[1].x);
     } else {
-      pan[NF * k + 2] = zs[1];
+      pan[NF * k + 2] = stream ? make_double2(-ps[1].x, -ps[1].y) : zs[1];
       pan[NF * k + 3] = make_double2(0.0, 0.0);
     }
   }

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 
   load_order(a, g, in, b, m, L);
   __syncthreads();
-  build_panel<NF>(pan, a, N, m, L, mode, in.coriolis);
+  build_panel<NF>(pan, a, N, m, L, mode, in.coriolis, in.stream != 0);
   if (NF == 5) {
     // fifth field: lambda^(-1/2) n_bar, l = max(m, 1)..N, real at m = 0 (n_bar formed
     // here from hbar_out[0] inside the step adjoint)
