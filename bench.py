@@ -279,6 +279,33 @@ def example2_timing(pkg, torch, T=60.0, N=100, nu=1e-4, omega=1.0, rtol=1e-3):
         wall = time.perf_counter() - t0
         log_ = s.adaptive_log()
         finite = bool(torch.isfinite(torch.view_as_real(a)).all())
+        # the same run with the paper's diagnostics at t = 10, 20, ..., 60: energy
+        # spectrum of u_{75;100}, approximate inertial manifold Phi_150(u_75) on an
+        # N' = 150 grid and its spectrum
+        N1, Np = 75, 150
+        aim = pkg.Sphere([(Np, 0, nu)], omega=omega, dt=1e-3, stream=stream)
+        Fp = aim.new_state()
+        Fp[I.index(Np, 3, 0)] = 1.0
+        s.adaptive_begin(a0, 0.0, rtol=rtol, atol=1e-6, forcing=(F, I.example2_force))
+        diag = {}
+        t0 = time.perf_counter()
+        for stop in range(10, int(T) + 1, 10):
+            a, _ = s.adaptive_advance(float(stop))
+            E = s.energy_spectrum(a).cpu()
+            phi = aim.inertial_manifold(a, N, N1, Fp * I.example2_force(float(stop)))
+            Ep = aim.energy_spectrum(phi).cpu()
+            L = torch.arange(Np + 1, dtype=torch.float64)
+            l4 = (L ** 4 * Ep)[N1 + 1:]
+            diag[f"t={stop}"] = {
+                "energy_L<=75": float(E[:N1 + 1].sum()),
+                "energy_75<L<=100": float(E[N1 + 1:].sum()),
+                "manifold_energy_75<L<=150": float(Ep.sum()),
+                "log10_L4E_manifold_L76_L150": [round(math.log10(float(l4[0])), 3),
+                                                round(math.log10(float(l4[-1])), 3)],
+            }
+        torch.cuda.synchronize()
+        wall_diag = time.perf_counter() - t0
+        aim.close()
         s.close()
     orders = collections.Counter(r[2] for r in log_ if r[4] == pkg.ATTEMPT_ACCEPTED)
     out.update({
@@ -295,6 +322,8 @@ def example2_timing(pkg, torch, T=60.0, N=100, nu=1e-4, omega=1.0, rtol=1e-3):
         "us_per_evaluation": round(1e6 * wall / st["evaluations"], 2),
         "fixed_step_us_per_evaluation": round(eval_us, 2),
         "finite": finite,
+        "with_diagnostics_wall_s": round(wall_diag, 4),
+        "diagnostics": diag,
     })
     return out
 

@@ -201,6 +201,7 @@ __host__ __device__ inline const float* analysis_table<float>(const GroupView& g
 
 // Dynamic LDS of the launches (validated against 64 KiB at init).
 size_t synthesis_lds_bytes(int N, int NF);
+size_t synthesis_lds_bytes(int N, int NF, bool otf);
 size_t ring_lds_bytes(int M);
 size_t analysis_lds_bytes(int nh);
 size_t synthesis_adjoint_lds_bytes(int nh);
