@@ -110,14 +110,229 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
   finish_degree(g, out, b, m, k, sx, sy);
 }
 
+// FP64 analysis with the Legendre values continued in registers (OTF): the
+// same sums, the loop transposed. Workgroup (m, tile of 64 degrees, member) as
+// above; wave w owns the degrees 16 w .. 16 w + 15 of the tile and its lanes are
+// latitudes, lane l taking p = l + 64 r for r < R (R = ceil(nh / 64)). Each lane
+// starts the recurrence of eq. (sph_har),
+//   Pbar[l,m] = a(l,m) mu Pbar[l-1,m] - (a(l,m) / a(l-1,m)) Pbar[l-2,m],
+// from the table rows of the tile's first two degrees, runs it to the wave's
+// degrees, and multiplies each value by its own latitude's folded spectrum
+// (We for even l-m, Wo for odd) held in registers; the sixteen complex sums are
+// then formed across the 64 lanes by a butterfly of register exchanges, which
+// leaves degree 8 b5 + 4 b4 + 2 b3 + b2 of the wave's block (b = lane bits) in
+// every lane with b1 = b0 = 0. The table traffic drops to two rows per tile.
+namespace {
+
+constexpr int kOtfDeg = 16;  // degrees per wave
+
+// Cross-lane moves of doubles in registers (no LDS): the gfx950 lane-half swaps
+// and DPP row mirrors / quad permutations, applied to both 32-bit halves.
+__device__ inline double lane_swap_sum32(double a, double b) {
+  // v_permlane32_swap: lanes 32..63 of a trade places with lanes 0..31 of b; the
+  // sum of the two results is a[l] + a[l ^ 32] in the lower half and
+  // b[l] + b[l ^ 32] in the upper half
+  const unsigned long long ai = __double_as_longlong(a), bi = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ai, (unsigned)bi, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
+  const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return a2 + b2;
+}
+__device__ inline double lane_swap_sum16(double a, double b) {
+  // v_permlane16_swap: odd 16-lane rows of a trade places with even rows of b
+  const unsigned long long ai = __double_as_longlong(a), bi = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ai, (unsigned)bi, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
+  const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return a2 + b2;
+}
+template <int CTRL>
+__device__ inline double lane_dpp(double v) {
+  const unsigned long long i = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)i, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(i >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+constexpr int kDppRowMirror = 0x140;      // lane i of a 16-lane row reads lane 15 - i
+constexpr int kDppRowHalfMirror = 0x141;  // lane i of an 8-lane half row reads lane 7 - i
+constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+
+// Sum over the 64 lanes of x[j], j < 16, by halving exchanges: partners differ
+// in lane bit 5 (swap), 4 (swap), 3 (row mirror, lane ^ 15), 2 (half-row
+// mirror, lane ^ 7), the lane keeping the half of the index set its own bit
+// selects; then plain sums over lane ^ 2 and lane ^ 1. On return x[0] holds the
+// sum for j = 8 b5 + 4 b4 + 2 b3 + b2 of the lane.
+__device__ inline void lane_butterfly16(double (&xr)[kOtfDeg], double (&xi)[kOtfDeg], int lane) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    xr[i] = lane_swap_sum32(xr[i], xr[i + 8]);
+    xi[i] = lane_swap_sum32(xi[i], xi[i + 8]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    xr[i] = lane_swap_sum16(xr[i], xr[i + 4]);
+    xi[i] = lane_swap_sum16(xi[i], xi[i + 4]);
+  }
+  {
+    const bool hi = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double kr = hi ? xr[i + 2] : xr[i], ki = hi ? xi[i + 2] : xi[i];
+      const double sr = hi ? xr[i] : xr[i + 2], si = hi ? xi[i] : xi[i + 2];
+      xr[i] = kr + lane_dpp<kDppRowMirror>(sr);
+      xi[i] = ki + lane_dpp<kDppRowMirror>(si);
+    }
+  }
+  {
+    const bool hi = (lane & 4) != 0;
+    const double kr = hi ? xr[1] : xr[0], ki = hi ? xi[1] : xi[0];
+    const double sr = hi ? xr[0] : xr[1], si = hi ? xi[0] : xi[1];
+    xr[0] = kr + lane_dpp<kDppRowHalfMirror>(sr);
+    xi[0] = ki + lane_dpp<kDppRowHalfMirror>(si);
+  }
+  xr[0] += lane_dpp<kDppQuadXor2>(xr[0]);
+  xi[0] += lane_dpp<kDppQuadXor2>(xi[0]);
+  xr[0] += lane_dpp<kDppQuadXor1>(xr[0]);
+  xi[0] += lane_dpp<kDppQuadXor1>(xi[0]);
+}
+
+template <int R>
+__global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
+  const int N = g.N, nh = g.nh;
+  const int ntile = (N + 1 + 63) / 64;
+  const int item = xcd_item(blockIdx.x, 4 * ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
+  if (m > N || tile * 64 > N - m) return;  // uniform across the workgroup
+  const int b = blockIdx.y;
+  extern __shared__ double2 wsh[];  // We [nh], Wo [nh], rc [64]
+  double2* rc = wsh + 2 * nh;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int kt = tile * 64;  // first degree offset k = l - m of the tile
+
+  // seeds first: their latency overlaps the prologue
+  const double* t = g.T2 + g.t2off[m] + (int64_t)tile * nh * kTile;
+  double x[R], P1[R], P2[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = lane + 64 * r;
+    x[r] = P1[r] = P2[r] = 0.0;
+    if (p < nh) {
+      P2[r] = t[(int64_t)p * kTile];
+      P1[r] = t[(int64_t)p * kTile + 1];  // rows hold 64 degrees (padded past L)
+      x[r] = g.mu[p];
+    }
+  }
+  // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p')
+  const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
+  for (int p = threadIdx.x; p < nh; p += blockDim.x) {
+    const double2 qn = Wb[(int64_t)p * (N + 1)];
+    const double2 qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+    wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
+    wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
+  }
+  // recurrence pairs of the tile's degrees (k >= 2 of the order)
+  if (threadIdx.x < 64) {
+    const int k = kt + threadIdx.x;
+    double2 c = make_double2(0.0, 0.0);
+    if (k >= 2) {
+      const double dl = (double)(m + k), dm = (double)m;
+      const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+      const double al1 =
+          sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
+      c = make_double2(al, al / al1);
+    }
+    rc[threadIdx.x] = c;
+  }
+  __syncthreads();
+  const int j0 = wave * kOtfDeg;  // the wave's first degree within the tile
+  if (kt + j0 > N - m) return;    // no degree of this wave is analysed
+  double2 We[R], Wo[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = lane + 64 * r;
+    We[r] = Wo[r] = make_double2(0.0, 0.0);
+    if (p < nh) {
+      We[r] = wsh[p];
+      Wo[r] = wsh[nh + p];
+    }
+  }
+  // advance every chain to the degrees j0, j0 + 1 of the tile (j0 is a
+  // multiple of 16: batches of four coefficient pairs read together)
+  for (int jb = 2; jb < j0 + 2; jb += 4) {
+    double2 c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = rc[jb + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double v = fma(c[u].x * x[r], P1[r], -c[u].y * P2[r]);
+        P2[r] = P1[r];
+        P1[r] = v;
+      }
+    }
+  }
+  // P2 = Pbar at j0, P1 at j0 + 1 (j0 is even: even, odd)
+  double sr[kOtfDeg], si[kOtfDeg];
+#pragma unroll
+  for (int i = 0; i < kOtfDeg; ++i) sr[i] = si[i] = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    sr[0] = fma(P2[r], We[r].x, sr[0]);
+    si[0] = fma(P2[r], We[r].y, si[0]);
+    sr[1] = fma(P1[r], Wo[r].x, sr[1]);
+    si[1] = fma(P1[r], Wo[r].y, si[1]);
+  }
+#pragma unroll
+  for (int i = 2; i < kOtfDeg; ++i) {
+    const double2 c = rc[j0 + i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double v = fma(c.x * x[r], P1[r], -c.y * P2[r]);
+      P2[r] = P1[r];
+      P1[r] = v;
+      const double2 w = (i & 1) ? Wo[r] : We[r];
+      sr[i] = fma(v, w.x, sr[i]);
+      si[i] = fma(v, w.y, si[i]);
+    }
+  }
+  lane_butterfly16(sr, si, lane);
+  if ((lane & 3) != 0) return;
+  const int j = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) +
+                ((lane >> 2) & 1);
+  const int k = kt + j0 + j;
+  if (k > N - m) return;
+  finish_degree(g, out, b, m, k, sr[0], si[0]);
+}
+
+}  // namespace
+
+size_t analysis_otf_lds_bytes(int nh) { return sizeof(double2) * (size_t)(2 * nh + 64); }
+
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s) {
   dim3 block(kAnalThreads);
   const int ntile = (g.N + 1 + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
-  if (g.precision == NSE_PREC_FP32)
+  if (g.precision == NSE_PREC_FP32) {
     hipLaunchKernelGGL(k_analysis<float>, grid, block, analysis_lds_bytes(g.nh), s, g, out);
-  else
-    hipLaunchKernelGGL(k_analysis<double>, grid, block, analysis_lds_bytes(g.nh), s, g, out);
+    return hipGetLastError();
+  }
+  const size_t lds = analysis_otf_lds_bytes(g.nh);
+  switch ((g.nh + 63) / 64) {
+    case 1: hipLaunchKernelGGL(k_analysis_otf<1>, grid, block, lds, s, g, out); break;
+    case 2: hipLaunchKernelGGL(k_analysis_otf<2>, grid, block, lds, s, g, out); break;
+    case 3: hipLaunchKernelGGL(k_analysis_otf<3>, grid, block, lds, s, g, out); break;
+    case 4: hipLaunchKernelGGL(k_analysis_otf<4>, grid, block, lds, s, g, out); break;
+    case 5: hipLaunchKernelGGL(k_analysis_otf<5>, grid, block, lds, s, g, out); break;
+    default: hipLaunchKernelGGL(k_analysis_otf<6>, grid, block, lds, s, g, out); break;
+  }
   return hipGetLastError();
 }
 
