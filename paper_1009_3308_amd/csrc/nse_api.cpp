@@ -975,7 +975,7 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
                "member %d: M = %d must be <= %d and factor into 2, 3 and 5", i, 2 * m.nlat, kMaxM);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
     }
-    if (synthesis_lds_bytes(m.N, 5) > 65536 || synthesis_lds_bytes(m.N, 4, true) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
+    if (synthesis_lds_bytes(m.N, 5, true) > 65536 || synthesis_lds_bytes(m.N, 4, true) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
         synthesis_adjoint_lds_bytes((m.nlat + 1) / 2) > 65536 ||
         analysis_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
         split_panel_lp_lds_bytes(m.N) > 65536 ||

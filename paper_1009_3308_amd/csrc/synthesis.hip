@@ -11,12 +11,12 @@
 // latitude yields the northern value E + O and the mirrored southern value
 // E - O. Output F[b][f][m][lat] is written latitude-contiguous.
 //
-// The Legendre values come from T1[m][l-m][p] in two ways. FP32 and the
-// adjoint's five-field mode stream the column of the table (coalesced across
-// the wavefront). The FP64 nonlinear and grid modes read only two table rows
-// per wave and continue the three-term recurrence in registers (OTF below): the
-// table is no longer streamed and the loop is bound by the LDS reads of the
-// panel, which is why the lanes take one to three latitudes each.
+// The Legendre values come from T1[m][l-m][p] in two ways. FP32 streams the
+// column of the table (coalesced across the wavefront). FP64 (nonlinear, grid
+// and the adjoint's five-field mode) reads only two table rows per wave and
+// continues the three-term recurrence in registers (OTF below): the table is no
+// longer streamed and the loop is bound by the LDS reads of the panel, which is
+// why the lanes of the four-field modes take one to three latitudes each.
 #include "spectral_ops.h"
 
 namespace nse {
@@ -247,8 +247,8 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
   const int ntile = (g.nh + 63) / 64;
   dim3 grid((g.N + 1) * ntile, g.nb);
   if (mode == SYNTH_ADJ)
-    hipLaunchKernelGGL((k_synthesis<double, 5>), grid, block, synthesis_lds_bytes(g.N, 5), s, g,
-                       in, mode);
+    hipLaunchKernelGGL((k_synthesis<double, 5, true>), grid, block,
+                       synthesis_lds_bytes(g.N, 5, true), s, g, in, mode);
   else if (g.precision == NSE_PREC_FP32)
     hipLaunchKernelGGL((k_synthesis<float, 4>), grid, block, synthesis_lds_bytes(g.N, 4), s, g,
                        in, mode);
