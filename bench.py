@@ -41,6 +41,7 @@ KERNEL_SOURCES = {
     "ring": ["paper_1009_3308_amd/csrc/ring_fft.hip",
              "paper_1009_3308_amd/csrc/nse_internal.h"],
     "analysis": ["paper_1009_3308_amd/csrc/analysis.hip",
+                 "paper_1009_3308_amd/csrc/lane_ops.h",
                  "paper_1009_3308_amd/csrc/spectral_ops.h",
                  "paper_1009_3308_amd/csrc/nse_internal.h"],
 }

@@ -20,6 +20,7 @@
 // each wave summing a quarter of the northern latitudes, partial sums added
 // through LDS. Orders are taken in XCD-local chunks of four neighbouring m so
 // that the strided reads of W[lat][m] share L2 lines.
+#include "lane_ops.h"
 #include "spectral_ops.h"
 
 namespace nse {
@@ -124,82 +125,7 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
 // every lane with b1 = b0 = 0. The table traffic drops to two rows per tile.
 namespace {
 
-constexpr int kOtfDeg = 16;  // degrees per wave
-
-// Cross-lane moves of doubles in registers (no LDS): the gfx950 lane-half swaps
-// and DPP row mirrors / quad permutations, applied to both 32-bit halves.
-__device__ inline double lane_swap_sum32(double a, double b) {
-  // v_permlane32_swap: lanes 32..63 of a trade places with lanes 0..31 of b; the
-  // sum of the two results is a[l] + a[l ^ 32] in the lower half and
-  // b[l] + b[l ^ 32] in the upper half
-  const unsigned long long ai = __double_as_longlong(a), bi = __double_as_longlong(b);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ai, (unsigned)bi, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane32_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
-  const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-  return a2 + b2;
-}
-__device__ inline double lane_swap_sum16(double a, double b) {
-  // v_permlane16_swap: odd 16-lane rows of a trade places with even rows of b
-  const unsigned long long ai = __double_as_longlong(a), bi = __double_as_longlong(b);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ai, (unsigned)bi, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane16_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
-  const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-  return a2 + b2;
-}
-template <int CTRL>
-__device__ inline double lane_dpp(double v) {
-  const unsigned long long i = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)i, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(i >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-constexpr int kDppRowMirror = 0x140;      // lane i of a 16-lane row reads lane 15 - i
-constexpr int kDppRowHalfMirror = 0x141;  // lane i of an 8-lane half row reads lane 7 - i
-constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
-constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
-
-// Sum over the 64 lanes of x[j], j < 16, by halving exchanges: partners differ
-// in lane bit 5 (swap), 4 (swap), 3 (row mirror, lane ^ 15), 2 (half-row
-// mirror, lane ^ 7), the lane keeping the half of the index set its own bit
-// selects; then plain sums over lane ^ 2 and lane ^ 1. On return x[0] holds the
-// sum for j = 8 b5 + 4 b4 + 2 b3 + b2 of the lane.
-__device__ inline void lane_butterfly16(double (&xr)[kOtfDeg], double (&xi)[kOtfDeg], int lane) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    xr[i] = lane_swap_sum32(xr[i], xr[i + 8]);
-    xi[i] = lane_swap_sum32(xi[i], xi[i + 8]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    xr[i] = lane_swap_sum16(xr[i], xr[i + 4]);
-    xi[i] = lane_swap_sum16(xi[i], xi[i + 4]);
-  }
-  {
-    const bool hi = (lane & 8) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double kr = hi ? xr[i + 2] : xr[i], ki = hi ? xi[i + 2] : xi[i];
-      const double sr = hi ? xr[i] : xr[i + 2], si = hi ? xi[i] : xi[i + 2];
-      xr[i] = kr + lane_dpp<kDppRowMirror>(sr);
-      xi[i] = ki + lane_dpp<kDppRowMirror>(si);
-    }
-  }
-  {
-    const bool hi = (lane & 4) != 0;
-    const double kr = hi ? xr[1] : xr[0], ki = hi ? xi[1] : xi[0];
-    const double sr = hi ? xr[0] : xr[1], si = hi ? xi[0] : xi[1];
-    xr[0] = kr + lane_dpp<kDppRowHalfMirror>(sr);
-    xi[0] = ki + lane_dpp<kDppRowHalfMirror>(si);
-  }
-  xr[0] += lane_dpp<kDppQuadXor2>(xr[0]);
-  xi[0] += lane_dpp<kDppQuadXor2>(xi[0]);
-  xr[0] += lane_dpp<kDppQuadXor1>(xr[0]);
-  xi[0] += lane_dpp<kDppQuadXor1>(xi[0]);
-}
+constexpr int kOtfDeg = kButterfly;  // degrees per wave
 
 template <int R>
 __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
