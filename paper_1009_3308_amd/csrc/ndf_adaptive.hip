@@ -15,6 +15,7 @@ __device__ inline double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
 // predictor of the next attempt, one state slot per thread.
 __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
   if (blockIdx.x == 0 && (int)threadIdx.x < a.nnorms) a.norms[threadIdx.x] = 0ull;
+  if (blockIdx.x == 0 && a.done && (int)threadIdx.x < a.nnorms / 4) a.done[threadIdx.x] = 0u;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.S) return;
   double2 D[kNdfDepth];
@@ -93,7 +94,25 @@ __device__ inline void block_max4(double v[4], unsigned long long* out) {
     unsigned long long bits = (unsigned long long)__double_as_longlong(r);
     if (r != r) bits = 0x7ff8000000000000ull;  // one positive NaN pattern
     atomicMax(out + q, bits);
+    __threadfence();
   }
+}
+
+// The last workgroup of a publishing launch copies the four norms of the sweep
+// to host memory and then the sequence word, which the host polls.
+__device__ inline void publish_norms(const NdfArgs& a) {
+  __syncthreads();  // this workgroup's atomics are complete
+  if (threadIdx.x != 0) return;
+  __threadfence();
+  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
+  if (atomicAdd(a.done + a.sweep, 1u) != nblocks - 1) return;
+  __threadfence();
+  volatile unsigned long long* pub = a.pub;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pub[4 * a.sweep + q] = atomicAdd(a.nrow + q, 0ull);
+  __threadfence_system();
+  pub[a.nnorms] = a.seq;
+  __threadfence_system();
 }
 
 // One corrector sweep (or F(t0, y0) in NDF_RHS mode) for the members of a group:
@@ -144,6 +163,7 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
     }
   }
   block_max4(v, a.nrow);
+  if (a.publish) publish_norms(a);
 }
 
 }  // namespace

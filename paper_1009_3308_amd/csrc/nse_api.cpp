@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -153,8 +154,10 @@ struct nse_ctx {
   double2* d_diag = nullptr;  // inertial manifold: band-limited input, its nonlinear term
   double2* d_ndf = nullptr;  // D [depth][S], then y0, psi, y, dA, dB, n (each S)
   int ndf_depth = 0;
-  unsigned long long* d_norms = nullptr;
-  unsigned long long* h_norms = nullptr;  // pinned host copy
+  unsigned long long* d_norms = nullptr;   // [4 x max sweeps] then block counters
+  unsigned long long* h_pub = nullptr;     // host-mapped: norms of every sweep + sequence word
+  unsigned long long* d_pub = nullptr;     // its device address
+  unsigned long long pub_seq = 0;
 };
 
 namespace {
@@ -633,9 +636,12 @@ nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
   NSE_HIP(c, dalloc(&c->d_ndf, (size_t)(depth + 6) * c->state_count));
   c->ndf_depth = depth;
   if (!c->d_norms) {
-    NSE_HIP(c, dalloc(&c->d_norms, 4 * kMaxNewton));
-    NSE_HIP(c, hipHostMalloc((void**)&c->h_norms, sizeof(unsigned long long) * 4 * kMaxNewton,
-                             hipHostMallocDefault));
+    // norms, then kMaxNewton 32-bit workgroup counters (half as many 64-bit slots)
+    NSE_HIP(c, dalloc(&c->d_norms, 4 * kMaxNewton + kMaxNewton / 2));
+    NSE_HIP(c, hipHostMalloc((void**)&c->h_pub, sizeof(unsigned long long) * (4 * kMaxNewton + 1),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(c->h_pub, 0, sizeof(unsigned long long) * (4 * kMaxNewton + 1));
+    NSE_HIP(c, hipHostGetDevicePointer((void**)&c->d_pub, c->h_pub, 0));
   }
   return NSE_OK;
 }
@@ -644,19 +650,33 @@ double2* ndf_buf(nse_ctx* c, int i) {  // 0 y0, 1 psi, 2 y, 3 dA, 4 dB, 5 n
   return c->d_ndf + (int64_t)(c->ndf_depth + i) * c->state_count;
 }
 
-// Squared norms of sweeps 0..rows-1 to the host (one wait on the stream).
+// Norms of sweeps 0..rows-1 (square roots of the published squares), after the
+// last corrector launch has published sequence number c->pub_seq: the host
+// polls the sequence word in mapped memory instead of waiting for the stream;
+// after two seconds of polling it waits for the stream and checks once more.
 nse_status read_norms(nse_ctx* c, int rows, double out[][4]) {
   const auto t0 = std::chrono::steady_clock::now();
-  NSE_HIP(c, hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(unsigned long long) * 4 * rows,
-                            hipMemcpyDeviceToHost, c->stream));
-  NSE_HIP(c, hipStreamSynchronize(c->stream));
+  volatile unsigned long long* seq = c->h_pub + 4 * kMaxNewton;
+  for (uint64_t spin = 1; *seq != c->pub_seq; ++spin) {
+    if ((spin & 4095) == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      NSE_HIP(c, hipStreamSynchronize(c->stream));
+      if (*seq != c->pub_seq)
+        return fail(c, NSE_ERR_HIP, "corrector norms were not published (sequence %llu)",
+                    (unsigned long long)c->pub_seq);
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   c->ad.stats.waits++;
   c->ad.stats.wait_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  volatile unsigned long long* pub = c->h_pub;
   for (int r = 0; r < rows; ++r)
     for (int q = 0; q < 4; ++q) {
+      const unsigned long long bits = pub[4 * r + q];
       double v;
-      std::memcpy(&v, &c->h_norms[4 * r + q], sizeof(double));
+      std::memcpy(&v, &bits, sizeof(double));
       out[r][q] = std::sqrt(v);
     }
   return NSE_OK;
@@ -672,6 +692,7 @@ NdfArgs ndf_args(nse_ctx* c) {
   a.thr2 = r * r;
   a.norms = c->d_norms;
   a.nnorms = 4 * kMaxNewton;
+  a.done = reinterpret_cast<unsigned int*>(c->d_norms + 4 * kMaxNewton);
   return a;
 }
 
@@ -720,7 +741,9 @@ void ndf_rescale(nse_ctx* c, double h_new) {
   ad.nconst = 0;
 }
 
-// One nonlinear evaluation n(src) into the n buffer.
+// One nonlinear evaluation n(src) into the n buffer (eager launches: replaying
+// the chain from a captured graph per sweep was measured slower at N = 100, the
+// graph launch costing the host more than the launches it replaces).
 nse_status ndf_eval(nse_ctx* c, const double2* src) {
   SynthInput in{};
   in.nsrc = 1;
@@ -752,7 +775,14 @@ nse_status ndf_correct(nse_ctx* c, int mode, int sweep, double h, const double2*
   a.h = h;
   a.ak = ndf_alpha(ad.k);
   a.nrow = c->d_norms + 4 * sweep;
-  for (auto& g : c->groups) NSE_HIP(c, launch_ndf_correct(g.view(), a, c->stream));
+  a.sweep = sweep;
+  a.done = reinterpret_cast<unsigned int*>(c->d_norms + 4 * kMaxNewton);
+  a.pub = c->d_pub;
+  a.seq = ++c->pub_seq;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    a.publish = gi + 1 == c->groups.size();  // stream order: the last launch ends the sweep
+    NSE_HIP(c, launch_ndf_correct(c->groups[gi].view(), a, c->stream));
+  }
   return NSE_OK;
 }
 
@@ -1066,7 +1096,7 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_ndf);
   (void)hipFree(ctx->d_diag);
   (void)hipFree(ctx->d_norms);
-  if (ctx->h_norms) (void)hipHostFree(ctx->h_norms);
+  if (ctx->h_pub) (void)hipHostFree(ctx->h_pub);
   delete ctx;
   return NSE_OK;
 }

@@ -154,6 +154,11 @@ struct NdfArgs {
   double h, ak, thr2;          // step, (1 - kappa_k) gamma_k, (atol / rtol)^2
   unsigned long long* nrow;    // squared weighted max norms of this sweep (IEEE bits):
                                // [0] d - dprev, [1] d, [2] D[k] + d (k > 1), [3] d - D[k+1] (k < kmax)
+  // publication of the sweep's norms to host memory by the launch's last workgroup
+  int publish, sweep;
+  unsigned int* done;          // [max sweeps] workgroup counters, zeroed by k_ndf_prepare
+  unsigned long long* pub;     // host-mapped: [4 x max sweeps] norms, then the sequence word
+  unsigned long long seq;
 };
 
 // Launchers (each enqueues on `s` and returns the launch status).

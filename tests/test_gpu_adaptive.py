@@ -271,3 +271,4 @@ def test_adaptive_forcing_callback_error_propagates():
     with pytest.raises(ZeroDivisionError):
         s.adaptive_advance(1.0)
     s.close()
+

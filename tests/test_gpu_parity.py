@@ -80,7 +80,9 @@ def test_legendre_table_matches_oracle(N):
     s.close()
 
 
-@pytest.mark.parametrize("N,nlat", [(9, 0), (31, 0), (31, 60), (255, 0)])
+# the FP64 synthesis takes 1, 2 or 3 latitudes per lane by grid size (nh <= 192,
+# 256 <= nh with nh % 192 != 0, nh = 384): (400, 640) and (511, 0) cover 2 and 3
+@pytest.mark.parametrize("N,nlat", [(9, 0), (31, 0), (31, 60), (255, 0), (400, 640), (511, 0)])
 def test_synthesis_matches_oracle(N, nlat):
     _say(f"case: synthesis N={N} nlat={nlat}")
     s = pkg.Sphere([(N, nlat, 0.0)], omega=OMEGA, dt=1e-3)
@@ -95,8 +97,11 @@ def test_synthesis_matches_oracle(N, nlat):
     s.close()
 
 
+# the FP64 analysis takes ceil(nh / 64) latitudes per lane: every count 1..6 occurs
+# ((127, 0): 2, (255, 0): 3, (300, 480): 4, (400, 640): 5, (511, 0): 6)
 @pytest.mark.parametrize("N,nlat", [(1, 0), (2, 0), (9, 0), (15, 0), (31, 0), (31, 60),
-                                    (63, 0), (127, 0), (255, 0), (511, 0)])
+                                    (63, 0), (127, 0), (255, 0), (300, 480), (400, 640),
+                                    (511, 0)])
 def test_nonlinear_matches_oracle(N, nlat):
     _say(f"case: nonlinear N={N} nlat={nlat}")
     s = pkg.Sphere([(N, nlat, 1e-3)], omega=OMEGA, dt=1e-3)
