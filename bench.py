@@ -53,19 +53,20 @@ def log(msg):
 
 def algorithmic_bytes(N, nlat, order, nsrc):
     """HBM bytes each kernel must move per launch (one member). The FP64
-    synthesis reads two table rows per wave (four waves per order) as seeds of the
-    Legendre recurrence instead of the table."""
+    synthesis reads two table rows per wave (four waves per order) and the FP64
+    analysis two per 16-degree block of a wave, as seeds of the Legendre
+    recurrence, instead of the table."""
     nh = (nlat + 1) // 2
     slots = (N + 1) * (N + 2) // 2
     F = 4 * nlat * (N + 1) * 16
     W = nlat * (N + 1) * 16
     seeds = 8 * 2 * 4 * nh * (N + 1)
-    tiles = sum((N + 1 - m + 63) // 64 for m in range(N + 1))
+    blocks = sum((N + 1 - m + 15) // 16 for m in range(N + 1))
     return {
         "synthesis": seeds + nsrc * slots * 16 + F,
         "ring": F + W,
-        # two table rows per 64-degree tile (recurrence seeds), ring spectra, states
-        "analysis": 8 * 2 * nh * tiles + W + (2 * (order + 1) + 1) * slots * 16,
+        # two table rows per 16-degree block (recurrence seeds), ring spectra, states
+        "analysis": 8 * 2 * nh * blocks + W + (2 * (order + 1) + 1) * slots * 16,
     }
 
 

@@ -117,12 +117,12 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis(GroupView g, AnalOutp
 // latitudes, lane l taking p = l + 64 r for r < R (R = ceil(nh / 64)). Each lane
 // starts the recurrence of eq. (sph_har),
 //   Pbar[l,m] = a(l,m) mu Pbar[l-1,m] - (a(l,m) / a(l-1,m)) Pbar[l-2,m],
-// from the table rows of the tile's first two degrees, runs it to the wave's
-// degrees, and multiplies each value by its own latitude's folded spectrum
+// from the T1 rows of the wave's own first two degrees (coalesced across the
+// lanes), and multiplies each value by its own latitude's folded spectrum
 // (We for even l-m, Wo for odd) held in registers; the sixteen complex sums are
 // then formed across the 64 lanes by a butterfly of register exchanges, which
 // leaves degree 8 b5 + 4 b4 + 2 b3 + b2 of the wave's block (b = lane bits) in
-// every lane with b1 = b0 = 0. The table traffic drops to two rows per tile.
+// every lane with b1 = b0 = 0. The table traffic drops to two rows per wave.
 namespace {
 
 constexpr int kOtfDeg = kButterfly;  // degrees per wave
@@ -142,17 +142,23 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
   const int wave = threadIdx.x >> 6;
   const int kt = tile * 64;  // first degree offset k = l - m of the tile
 
-  // seeds first: their latency overlaps the prologue
-  const double* t = g.T2 + g.t2off[m] + (int64_t)tile * nh * kTile;
+  const int j0 = wave * kOtfDeg;        // the wave's first degree within the tile
+  const bool active = kt + j0 <= N - m;  // some degree of this wave is analysed
+  // seeds first, their latency overlapping the prologue: the wave's first two
+  // degrees, two coalesced rows of T1 (it holds k = 0 .. N + 1 - m)
   double x[R], P1[R], P2[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int p = lane + 64 * r;
-    x[r] = P1[r] = P2[r] = 0.0;
-    if (p < nh) {
-      P2[r] = t[(int64_t)p * kTile];
-      P1[r] = t[(int64_t)p * kTile + 1];  // rows hold 64 degrees (padded past L)
-      x[r] = g.mu[p];
+  for (int r = 0; r < R; ++r) x[r] = P1[r] = P2[r] = 0.0;
+  if (active) {
+    const double* t = g.T1 + t1_order_offset(N, m, nh) + (int64_t)(kt + j0) * nh;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = lane + 64 * r;
+      if (p < nh) {
+        P2[r] = t[p];
+        P1[r] = t[nh + p];
+        x[r] = g.mu[p];
+      }
     }
   }
   // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p')
@@ -177,8 +183,7 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     rc[threadIdx.x] = c;
   }
   __syncthreads();
-  const int j0 = wave * kOtfDeg;  // the wave's first degree within the tile
-  if (kt + j0 > N - m) return;    // no degree of this wave is analysed
+  if (!active) return;
   double2 We[R], Wo[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -187,22 +192,6 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     if (p < nh) {
       We[r] = wsh[p];
       Wo[r] = wsh[nh + p];
-    }
-  }
-  // advance every chain to the degrees j0, j0 + 1 of the tile (j0 is a
-  // multiple of 16: batches of four coefficient pairs read together)
-  for (int jb = 2; jb < j0 + 2; jb += 4) {
-    double2 c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = rc[jb + u];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double v = fma(c[u].x * x[r], P1[r], -c[u].y * P2[r]);
-        P2[r] = P1[r];
-        P1[r] = v;
-      }
     }
   }
   // P2 = Pbar at j0, P1 at j0 + 1 (j0 is even: even, odd)
