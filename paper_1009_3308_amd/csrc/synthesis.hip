@@ -242,6 +242,201 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   }
 }
 
+// FP64 nonlinear-mode synthesis with the colatitude derivatives taken on the
+// Legendre side. With D[l] = sin(theta) dPbar[l,m]/dtheta, which the derivative
+// relation above and the recurrence turn into
+//   D[l] = l mu Pbar[l,m] - (2l+1) e(l) Pbar[l-1,m],
+// the four fields are
+//   f0 = i m sum psi[l] Pbar,  f1 = sum psi[l] D,  f2 = sum zeta_a[l] D,  f3 = i m sum zeta_a[l] Pbar
+// over l = m..N, with zeta_a[l] = lambda_l psi[l] plus the Coriolis fold at
+// (1, 0), which only f2 sees (f3 carries the factor m = 0 there). Per degree the
+// loop reads psi[l] and two coefficient pairs from LDS, three reads where the
+// panel form needs five, and D[l] has the parity opposite to Pbar[l,m] under
+// mu -> -mu, so its terms go to the other half of the even/odd split. Tiles,
+// latitudes per lane (R) and the cross-wave sums are those of k_synthesis.
+template <int R>
+__global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
+  constexpr int kRed = 16;
+  constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
+  const int N = g.N, nh = g.nh, nlat = g.nlat;
+  const int ntile = (nh + 64 * R - 1) / (64 * R);
+  const int m = blockIdx.x / ntile;
+  const int tile = blockIdx.x - m * ntile;
+  const int b = blockIdx.y;
+  const int L = N + 2 - m;  // load_order's range
+  const int K = N + 1 - m;  // degrees m .. N
+  extern __shared__ double2 sh[];
+  double2* a = sh;                          // [L + 1] alpha[l]
+  double2* psi = a + (N + 3);               // [K + kOtfBatch] psi[l] = lambda^(-1/2) alpha[l]
+  double2* rc = psi + (N + 1 + kOtfBatch);  // [K + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
+  double2* dc = rc + (N + 1 + kOtfBatch);   // [K + kOtfBatch] ((2l+1) e(l), lambda_l)
+
+  load_order(a, g, in, b, m, L);
+  __syncthreads();
+  const double dm = (double)m;
+  for (int k = threadIdx.x; k < K + kOtfBatch; k += blockDim.x) {
+    double2 ps = make_double2(0.0, 0.0), c = ps, d = ps;
+    if (k < K) {
+      const double dl = (double)(m + k);
+      const double lam = dl * (dl + 1.0);
+      if (m + k >= 1) {
+        const double r = 1.0 / sqrt(lam);
+        ps = make_double2(a[k].x * r, a[k].y * r);
+      }
+      if (k >= 1) {
+        // a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)) = 1 / e(l); a(l-1,m) is
+        // infinite at k = 1, where the ratio multiplies Pbar[m-1,m] = 0
+        const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+        double ratio = 0.0;
+        if (k >= 2) {
+          const double al1 =
+              sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
+          ratio = al / al1;
+        }
+        c = make_double2(al, ratio);
+        d = make_double2((2.0 * dl + 1.0) / al, lam);
+      } else {
+        d = make_double2(0.0, lam);  // e(m) = 0
+      }
+    }
+    psi[k] = ps;
+    rc[k] = c;
+    dc[k] = d;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int pbase = tile * 64 * R + lane;  // latitude of slot r: pbase + 64 r
+  const int chunk = ((K + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
+  const int k0 = wave * chunk;  // even
+  const int k1 = min(K, k0 + chunk);
+  // acc[r][4 f + 2 q + c]: field f, q = 0 even / 1 odd part, c = 0 re / 1 im
+  double acc[R][kRed];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < kRed; ++i) acc[r][i] = 0.0;
+  if (k0 < k1) {
+    // seeds: Pbar at k0 (table row k0) and k0 - 1 (row k0 - 1, zero below m)
+    const double* t = g.T1 + t1_order_offset(N, m, nh);
+    double P1[R], P2[R], x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = pbase + 64 * r;
+      P1[r] = P2[r] = x[r] = 0.0;
+      if (p < nh) {
+        P1[r] = t[(int64_t)k0 * nh + p];
+        if (k0 >= 1) P2[r] = t[(int64_t)(k0 - 1) * nh + p];
+        x[r] = g.mu[p];
+      }
+    }
+    {
+      // degree k0 (even): Pbar terms to the even part, D terms to the odd part
+      const double2 ps = psi[k0], d = dc[k0];
+      const double2 za = make_double2(d.y * ps.x, d.y * ps.y);
+      const double dl = (double)(m + k0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double D = fma(dl * x[r], P1[r], -d.x * P2[r]);
+        acc[r][0] = fma(P1[r], ps.x, acc[r][0]);
+        acc[r][1] = fma(P1[r], ps.y, acc[r][1]);
+        acc[r][6] = fma(D, ps.x, acc[r][6]);
+        acc[r][7] = fma(D, ps.y, acc[r][7]);
+        acc[r][10] = fma(D, za.x, acc[r][10]);
+        acc[r][11] = fma(D, za.y, acc[r][11]);
+        acc[r][12] = fma(P1[r], za.x, acc[r][12]);
+        acc[r][13] = fma(P1[r], za.y, acc[r][13]);
+      }
+    }
+    if (m == 0 && k0 == 0 && k1 > 1) {
+      // Coriolis fold: zeta_a[1,0] += coriolis, seen by f2 through D[1]
+      // (degree 1 is odd, so D[1] is even); Pbar[1,0] = a(1,0) mu Pbar[0,0]
+      const double2 c = rc[1], d = dc[1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double p1 = c.x * x[r] * P1[r];
+        const double D = fma(x[r], p1, -d.x * P1[r]);
+        acc[r][8] = fma(in.coriolis, D, acc[r][8]);
+      }
+    }
+    // degrees k0 + 1 .. k1 - 1 in batches of kB (kb odd: degree kb + u is odd
+    // for even u); entries past k1 are padding and are not accumulated
+    for (int kb = k0 + 1; kb < k1; kb += kB) {
+      double2 c[kB], ps[kB], d[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        c[u] = rc[kb + u];
+        ps[u] = psi[kb + u];
+        d[u] = dc[kb + u];
+      }
+      double2 za[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) za[u] = make_double2(d[u].y * ps[u].x, d[u].y * ps[u].y);
+      const double dl0 = (double)(m + kb);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const double v = fma(c[u].x * x[r], P1[r], -c[u].y * P2[r]);
+          P2[r] = P1[r];
+          P1[r] = v;
+          if (kb + u < k1) {
+            const int qp = 2 * ((u + 1) & 1);  // part of the Pbar terms
+            const int qd = 2 - qp;             // part of the D terms
+            const double D = fma((dl0 + u) * x[r], v, -d[u].x * P2[r]);
+            acc[r][0 + qp] = fma(v, ps[u].x, acc[r][0 + qp]);
+            acc[r][1 + qp] = fma(v, ps[u].y, acc[r][1 + qp]);
+            acc[r][4 + qd] = fma(D, ps[u].x, acc[r][4 + qd]);
+            acc[r][5 + qd] = fma(D, ps[u].y, acc[r][5 + qd]);
+            acc[r][8 + qd] = fma(D, za[u].x, acc[r][8 + qd]);
+            acc[r][9 + qd] = fma(D, za[u].y, acc[r][9 + qd]);
+            acc[r][12 + qp] = fma(v, za[u].x, acc[r][12 + qp]);
+            acc[r][13 + qp] = fma(v, za[u].y, acc[r][13 + qp]);
+          }
+        }
+      }
+    }
+  }
+  // cross-wave sums through LDS (the coefficient arrays are no longer needed);
+  // wave w finishes field w of its latitudes; f0 and f3 take the factor i m
+  double* red = reinterpret_cast<double*>(sh);  // [wave][kRed][64]
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRed; ++i) red[(wave * kRed + i) * 64 + lane] = acc[r][i];
+    __syncthreads();
+    const int p = pbase + 64 * r;
+    if (p < nh) {
+      const int f = wave;
+      double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+#pragma unroll
+      for (int w = 0; w < kSynthWaves; ++w) {
+        er += red[(w * kRed + 4 * f + 0) * 64 + lane];
+        ei += red[(w * kRed + 4 * f + 1) * 64 + lane];
+        orr += red[(w * kRed + 4 * f + 2) * 64 + lane];
+        oi += red[(w * kRed + 4 * f + 3) * 64 + lane];
+      }
+      double2 vn = make_double2(er + orr, ei + oi), vs = make_double2(er - orr, ei - oi);
+      if (f == 0 || f == 3) {
+        vn = make_double2(-dm * vn.y, dm * vn.x);
+        vs = make_double2(-dm * vs.y, dm * vs.x);
+      }
+      double2* out = g.F + ((int64_t)(b * 4 + f) * (N + 1) + m) * nlat;
+      out[p] = vn;
+      const int psouth = nlat - 1 - p;
+      if (psouth != p) out[psouth] = vs;
+    }
+  }
+}
+
+size_t synthesis_adv_lds_bytes(int N) {
+  const int arrays = (N + 3) + 3 * (N + 1 + kOtfBatch);
+  const int red = kSynthWaves * 16 * 64 / 2;
+  return sizeof(double2) * (size_t)(arrays > red ? arrays : red);
+}
+
 hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, hipStream_t s) {
   dim3 block(kSynthThreads);
   const int ntile = (g.nh + 63) / 64;
@@ -252,7 +447,13 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
   else if (g.precision == NSE_PREC_FP32)
     hipLaunchKernelGGL((k_synthesis<float, 4>), grid, block, synthesis_lds_bytes(g.N, 4), s, g,
                        in, mode);
-  else if (g.nh >= 384 && g.nh % 192 == 0) {
+  else if (mode == SYNTH_NONLINEAR && g.nh < 256) {
+    // one latitude per lane: the loop is bound by the LDS reads, and the
+    // derivative-on-Legendre form reads three values per degree instead of five
+    // (T255: 14.2 -> 13.8 us); with two or three latitudes per lane the panel
+    // form's fewer FMAs per latitude win (T511: 38.6 us against 44.4 us)
+    hipLaunchKernelGGL(k_synthesis_adv<1>, grid, block, synthesis_adv_lds_bytes(g.N), s, g, in);
+  } else if (g.nh >= 384 && g.nh % 192 == 0) {
     // large grids: three latitudes per lane (measured best at nh = 384; at
     // nh <= 192 one latitude per lane is faster, the grid having too few tiles)
     dim3 grid3((g.N + 1) * (g.nh / 192), g.nb);
