@@ -161,13 +161,14 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       }
     }
   }
-  // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p')
+  // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p');
+  // the thread's first pair is requested before the coefficient pairs are
+  // computed, so that their square roots overlap its latency
   const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
-  for (int p = threadIdx.x; p < nh; p += blockDim.x) {
-    const double2 qn = Wb[(int64_t)p * (N + 1)];
-    const double2 qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
-    wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
-    wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
+  double2 qn = make_double2(0.0, 0.0), qs = qn;
+  if ((int)threadIdx.x < nh) {
+    qn = Wb[(int64_t)threadIdx.x * (N + 1)];
+    qs = Wb[(int64_t)(g.nlat - 1 - (int)threadIdx.x) * (N + 1)];
   }
   // recurrence pairs of the tile's degrees (k >= 2 of the order)
   if (threadIdx.x < 64) {
@@ -181,6 +182,14 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       c = make_double2(al, al / al1);
     }
     rc[threadIdx.x] = c;
+  }
+  for (int p = threadIdx.x; p < nh; p += blockDim.x) {
+    if (p != (int)threadIdx.x) {
+      qn = Wb[(int64_t)p * (N + 1)];
+      qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+    }
+    wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
+    wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
   }
   __syncthreads();
   if (!active) return;

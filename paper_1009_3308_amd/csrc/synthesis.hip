@@ -263,26 +263,55 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   const int m = blockIdx.x / ntile;
   const int tile = blockIdx.x - m * ntile;
   const int b = blockIdx.y;
-  const int L = N + 2 - m;  // load_order's range
   const int K = N + 1 - m;  // degrees m .. N
   extern __shared__ double2 sh[];
-  double2* a = sh;                          // [L + 1] alpha[l]
-  double2* psi = a + (N + 3);               // [K + kOtfBatch] psi[l] = lambda^(-1/2) alpha[l]
+  double2* psi = sh;                        // [K + kOtfBatch] psi[l] = lambda^(-1/2) alpha[l]
   double2* rc = psi + (N + 1 + kOtfBatch);  // [K + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
   double2* dc = rc + (N + 1 + kOtfBatch);   // [K + kOtfBatch] ((2l+1) e(l), lambda_l)
 
-  load_order(a, g, in, b, m, L);
-  __syncthreads();
-  const double dm = (double)m;
-  for (int k = threadIdx.x; k < K + kOtfBatch; k += blockDim.x) {
-    double2 ps = make_double2(0.0, 0.0), c = ps, d = ps;
-    if (k < K) {
-      const double dl = (double)(m + k);
-      const double lam = dl * (dl + 1.0);
-      if (m + k >= 1) {
-        const double r = 1.0 / sqrt(lam);
-        ps = make_double2(a[k].x * r, a[k].y * r);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int pbase = tile * 64 * R + lane;  // latitude of slot r: pbase + 64 r
+  const int chunk = ((K + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
+  const int k0 = wave * chunk;  // even
+  const int k1 = min(K, k0 + chunk);
+  // The prologue's three latencies overlap: the seed rows and the input states
+  // are requested first, the recurrence coefficients (square roots and
+  // divisions) are computed while they arrive, and psi is formed from the
+  // states directly, so one barrier precedes the loop.
+  // seeds: Pbar at k0 (table row k0) and k0 - 1 (row k0 - 1, zero below m)
+  double P1[R], P2[R], x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) P1[r] = P2[r] = x[r] = 0.0;
+  if (k0 < k1) {
+    const double* t = g.T1 + t1_order_offset(N, m, nh);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = pbase + 64 * r;
+      if (p < nh) {
+        P1[r] = t[(int64_t)k0 * nh + p];
+        if (k0 >= 1) P2[r] = t[(int64_t)(k0 - 1) * nh + p];
+        x[r] = g.mu[p];
       }
+    }
+  }
+  const double dm = (double)m;
+  const int64_t base = g.off[b] + coeff_offset(N, m);
+  for (int k = threadIdx.x; k < K + kOtfBatch; k += blockDim.x) {
+    const int l = m + k;
+    // input state alpha[l] = sum_i coef_i src_i[l] (l = 1..N; real at m = 0)
+    double2 src[kMaxSources];
+#pragma unroll
+    for (int i = 0; i < kMaxSources; ++i) {
+      src[i] = make_double2(0.0, 0.0);
+      if (i < in.nsrc && k < K && l >= 1) src[i] = in.src[i][base + k];
+    }
+    double2 c = make_double2(0.0, 0.0), d = c;
+    double r = 0.0;
+    if (k < K) {
+      const double dl = (double)l;
+      const double lam = dl * (dl + 1.0);
+      if (l >= 1) r = 1.0 / sqrt(lam);
       if (k >= 1) {
         // a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)) = 1 / e(l); a(l-1,m) is
         // infinite at k = 1, where the ratio multiplies Pbar[m-1,m] = 0
@@ -299,18 +328,21 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
         d = make_double2(0.0, lam);  // e(m) = 0
       }
     }
-    psi[k] = ps;
+    double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < kMaxSources; ++i) {
+      if (i < in.nsrc) {
+        v.x += in.coef[i] * src[i].x;
+        v.y += in.coef[i] * src[i].y;
+      }
+    }
+    if (m == 0) v.y = 0.0;
+    psi[k] = make_double2(v.x * r, v.y * r);
     rc[k] = c;
     dc[k] = d;
   }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int pbase = tile * 64 * R + lane;  // latitude of slot r: pbase + 64 r
-  const int chunk = ((K + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
-  const int k0 = wave * chunk;  // even
-  const int k1 = min(K, k0 + chunk);
   // acc[r][4 f + 2 q + c]: field f, q = 0 even / 1 odd part, c = 0 re / 1 im
   double acc[R][kRed];
 #pragma unroll
@@ -318,19 +350,6 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
 #pragma unroll
     for (int i = 0; i < kRed; ++i) acc[r][i] = 0.0;
   if (k0 < k1) {
-    // seeds: Pbar at k0 (table row k0) and k0 - 1 (row k0 - 1, zero below m)
-    const double* t = g.T1 + t1_order_offset(N, m, nh);
-    double P1[R], P2[R], x[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int p = pbase + 64 * r;
-      P1[r] = P2[r] = x[r] = 0.0;
-      if (p < nh) {
-        P1[r] = t[(int64_t)k0 * nh + p];
-        if (k0 >= 1) P2[r] = t[(int64_t)(k0 - 1) * nh + p];
-        x[r] = g.mu[p];
-      }
-    }
     {
       // degree k0 (even): Pbar terms to the even part, D terms to the odd part
       const double2 ps = psi[k0], d = dc[k0];
@@ -432,7 +451,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
 }
 
 size_t synthesis_adv_lds_bytes(int N) {
-  const int arrays = (N + 3) + 3 * (N + 1 + kOtfBatch);
+  const int arrays = 3 * (N + 1 + kOtfBatch);
   const int red = kSynthWaves * 16 * 64 / 2;
   return sizeof(double2) * (size_t)(arrays > red ? arrays : red);
 }
