@@ -57,12 +57,15 @@ typedef enum {
   NSE_ERR_STATE = 6        /* call not valid in the context's current state   */
 } nse_status;
 
-/* Precision of the Legendre contractions (a8/a2 of the hot path). The Legendre
- * recurrences, quadrature weights, FFTs, grid products and the viscous update
- * always run in FP64. */
+/* Precision of the Legendre contractions (the direct synthesis and analysis sums
+ * of Section 4.2). The quadrature weights, FFTs, grid products and the viscous
+ * update always run in FP64, and so do the Legendre values: FP64 and FP32
+ * continue the three-term recurrence in FP64 registers from FP64 seed rows;
+ * BF16X3 reads the FP64 table rounded once to FP32. */
 enum {
-  NSE_PREC_FP64 = 0,  /* FP64 table, FP64 accumulation                         */
-  NSE_PREC_FP32 = 1,  /* FP32 table and operands, FP32 accumulation            */
+  NSE_PREC_FP64 = 0,  /* FP64 products, FP64 accumulation                      */
+  NSE_PREC_FP32 = 1,  /* values and coefficients rounded to FP32, FP32 products
+                         and per-wave accumulation, FP64 cross-wave sums      */
   NSE_PREC_BF16X3 = 2 /* operands split into three bf16 pieces, MFMA, FP32 acc */
 };
 

@@ -45,12 +45,29 @@ constexpr int kDppRowHalfMirror = 0x141;  // lane i of an 8-lane half row reads 
 constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
 
+// Single-precision forms of the same moves (one 32-bit register each).
+__device__ inline float lane_swap_sum32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float lane_swap_sum16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ inline float lane_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Sum over the 64 lanes of x[j], j < 16, by halving exchanges: partners differ
 // in lane bit 5 (swap), 4 (swap), 3 (row mirror, lane ^ 15), 2 (half-row
 // mirror, lane ^ 7), the lane keeping the half of the index set its own bit
 // selects; then plain sums over lane ^ 2 and lane ^ 1. On return x[0] holds the
-// sum for j = 8 b5 + 4 b4 + 2 b3 + b2 of the lane.
-__device__ inline void lane_butterfly16(double (&xr)[kButterfly], double (&xi)[kButterfly], int lane) {
+// sum for j = 8 b5 + 4 b4 + 2 b3 + b2 of the lane. T is double or float.
+template <typename T>
+__device__ inline void lane_butterfly16(T (&xr)[kButterfly], T (&xi)[kButterfly], int lane) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     xr[i] = lane_swap_sum32(xr[i], xr[i + 8]);
@@ -65,16 +82,16 @@ __device__ inline void lane_butterfly16(double (&xr)[kButterfly], double (&xi)[k
     const bool hi = (lane & 8) != 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const double kr = hi ? xr[i + 2] : xr[i], ki = hi ? xi[i + 2] : xi[i];
-      const double sr = hi ? xr[i] : xr[i + 2], si = hi ? xi[i] : xi[i + 2];
+      const T kr = hi ? xr[i + 2] : xr[i], ki = hi ? xi[i + 2] : xi[i];
+      const T sr = hi ? xr[i] : xr[i + 2], si = hi ? xi[i] : xi[i + 2];
       xr[i] = kr + lane_dpp<kDppRowMirror>(sr);
       xi[i] = ki + lane_dpp<kDppRowMirror>(si);
     }
   }
   {
     const bool hi = (lane & 4) != 0;
-    const double kr = hi ? xr[1] : xr[0], ki = hi ? xi[1] : xi[0];
-    const double sr = hi ? xr[0] : xr[1], si = hi ? xi[0] : xi[1];
+    const T kr = hi ? xr[1] : xr[0], ki = hi ? xi[1] : xi[0];
+    const T sr = hi ? xr[0] : xr[1], si = hi ? xi[0] : xi[1];
     xr[0] = kr + lane_dpp<kDppRowHalfMirror>(sr);
     xi[0] = ki + lane_dpp<kDppRowHalfMirror>(si);
   }

@@ -279,11 +279,11 @@ nse_status build_group(nse_ctx* c, Group& g) {
                        hipMemcpyHostToDevice));
   NSE_HIP(c, dalloc(&g.d_T1, ts1));
   NSE_HIP(c, dalloc(&g.d_T2, ts2));
-  if (c->params.precision != NSE_PREC_FP64) {
+  if (c->params.precision == NSE_PREC_BF16X3) {
+    // FP32 copies of the tables, split into bf16 pieces in registers (the FP64
+    // and FP32 modes continue the recurrences from FP64 seed rows instead)
     NSE_HIP(c, dalloc(&g.d_T1f, ts1));
     NSE_HIP(c, dalloc(&g.d_T2f, ts2));
-  }
-  if (c->params.precision == NSE_PREC_BF16X3) {
     // per order: ceil(L / 32) blocks x 3 pieces x 64 lanes of 4 bf16
     std::vector<int64_t> off(g.N + 2, 0);
     for (int m = 0; m <= g.N; ++m) off[m + 1] = off[m] + (int64_t)((g.N + 2 - m + 31) / 32) * 3 * 64;
@@ -1005,9 +1005,9 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
                "member %d: M = %d must be <= %d and factor into 2, 3 and 5", i, 2 * m.nlat, kMaxM);
       return init_fail(NSE_ERR_UNSUPPORTED, buf);
     }
-    if (synthesis_lds_bytes(m.N, 5, true) > 65536 || synthesis_lds_bytes(m.N, 4, true) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
+    if (synthesis_lds_bytes(m.N, 5) > 65536 || synthesis_lds_bytes(m.N, 4) > 65536 || ring_lds_bytes(2 * m.nlat) > 65536 ||
         synthesis_adjoint_lds_bytes((m.nlat + 1) / 2) > 65536 ||
-        analysis_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
+        analysis_otf_lds_bytes((m.nlat + 1) / 2) > 65536 || synthesis_lp_lds_bytes(m.N) > 65536 ||
         split_panel_lp_lds_bytes(m.N) > 65536 ||
         analysis_lp_lds_bytes((m.nlat + 1) / 2) > 65536) {
       snprintf(buf, sizeof buf, "member %d: N = %d exceeds the largest supported truncation", i,

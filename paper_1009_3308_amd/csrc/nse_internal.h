@@ -191,24 +191,10 @@ hipError_t launch_inertial_manifold(const GroupView& g, const double2* n, const 
                                     int N1, double omega, double2* phi, hipStream_t s);
 hipError_t launch_ndf_correct(const GroupView& g, const NdfArgs& a, hipStream_t s);
 
-template <typename TT>
-__host__ __device__ inline const TT* synthesis_table(const GroupView& g);
-template <>
-__host__ __device__ inline const double* synthesis_table<double>(const GroupView& g) { return g.T1; }
-template <>
-__host__ __device__ inline const float* synthesis_table<float>(const GroupView& g) { return g.T1f; }
-template <typename TT>
-__host__ __device__ inline const TT* analysis_table(const GroupView& g);
-template <>
-__host__ __device__ inline const double* analysis_table<double>(const GroupView& g) { return g.T2; }
-template <>
-__host__ __device__ inline const float* analysis_table<float>(const GroupView& g) { return g.T2f; }
-
 // Dynamic LDS of the launches (validated against 64 KiB at init).
 size_t synthesis_lds_bytes(int N, int NF);
-size_t synthesis_lds_bytes(int N, int NF, bool otf);
 size_t ring_lds_bytes(int M);
-size_t analysis_lds_bytes(int nh);
+size_t analysis_otf_lds_bytes(int nh);
 size_t synthesis_adjoint_lds_bytes(int nh);
 size_t synthesis_lp_lds_bytes(int N);
 size_t split_panel_lp_lds_bytes(int N);

@@ -11,20 +11,23 @@
 // latitude yields the northern value E + O and the mirrored southern value
 // E - O. Output F[b][f][m][lat] is written latitude-contiguous.
 //
-// The Legendre values come from T1[m][l-m][p] in two ways. FP32 streams the
-// column of the table (coalesced across the wavefront). FP64 (nonlinear, grid
-// and the adjoint's five-field mode) reads only two table rows per wave and
-// continues the three-term recurrence in registers (OTF below): the table is no
-// longer streamed and the loop is bound by the LDS reads of the panel, which is
-// why the lanes of the four-field modes take one to three latitudes each.
+// The Legendre values are not streamed from the table T1[m][l-m][p]: each wave
+// reads two table rows at the start of its degree range and continues the
+// three-term recurrence in FP64 registers, so the loop is bound by the LDS reads
+// of the panel, which is why the lanes of the four-field modes take one to three
+// latitudes each.
+#include <type_traits>
+
 #include "spectral_ops.h"
 
 namespace nse {
 
 constexpr int kSynthWaves = 4;
 constexpr int kSynthThreads = 64 * kSynthWaves;
-constexpr int kBatch = 8;  // table rows per load batch (even)
 constexpr int kOtfBatch = 4;  // degrees per recurrence batch (even)
+// panel entries each thread rounds to FP32 (four fields: N + 2 + kOtfBatch
+// degrees; launch_synthesis rejects larger N)
+constexpr int kPanelConvPerThread = 10;
 
 // NF fields: per lane 4 NF partial sums (NF fields x (E, O) x (re, im)).
 // The panel [L][NF] double2 is reused afterwards for the cross-wave reduction.
@@ -34,28 +37,28 @@ __host__ __device__ inline int synth_pan_slots(int N, int NF) {
   return pan > red ? pan : red;
 }
 
-// LDS: coefficients, panel (reused for the reduction) and, with OTF, the
-// recurrence coefficients of the order.
-size_t synthesis_lds_bytes(int N, int NF, bool otf) {
-  return sizeof(double2) *
-         (size_t)((N + 3) + synth_pan_slots(N, NF) + (otf ? N + 2 + kOtfBatch : 0));
+// LDS: coefficients, panel (reused for the reduction) and the recurrence
+// coefficients of the order.
+size_t synthesis_lds_bytes(int N, int NF) {
+  return sizeof(double2) * (size_t)((N + 3) + synth_pan_slots(N, NF) + N + 2 + kOtfBatch);
 }
-size_t synthesis_lds_bytes(int N, int NF) { return synthesis_lds_bytes(N, NF, false); }
 
-// TT: element type of the table and of the products and accumulation (double
-// for NSE_PREC_FP64, float for NSE_PREC_FP32); the cross-wave sums are FP64.
+// TT: type of the products and of the per-wave accumulation (double for
+// NSE_PREC_FP64; float for NSE_PREC_FP32, where the panel is rounded to FP32 once
+// and each Legendre value before its products); the recurrence and the
+// cross-wave sums are FP64 in both.
 // NF: 4 (nonlinear and grid modes) or 5 (adjoint mode).
-// OTF (FP64 only): the Legendre values are not streamed from T1 but continued
-// in registers by the three-term recurrence of eq. (sph_har),
+// The Legendre values are continued in registers by the three-term recurrence of
+// eq. (sph_har),
 //   Pbar[l,m] = a(l,m) mu Pbar[l-1,m] - (a(l,m) / a(l-1,m)) Pbar[l-2,m],
 //   a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)),
 // from two table rows at the start of each wave's degree range (seeds), with
 // the coefficient pairs of the order in LDS. The table traffic drops from the
 // whole T1 to two rows per wave.
-// R (OTF only): latitudes per lane (tiles of 64 R latitudes, lane l taking
-// l, l + 64, ...): every panel value read from LDS then serves R latitudes,
-// which is what bounds the OTF loop (the LDS, shared by the four SIMDs).
-template <typename TT, int NF, bool OTF = false, int R = 1>
+// R: latitudes per lane (tiles of 64 R latitudes, lane l taking l, l + 64, ...):
+// every panel value read from LDS then serves R latitudes, which is what bounds
+// the loop (the LDS, shared by the four SIMDs).
+template <typename TT, int NF, int R = 1>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthInput in,
                                                               int mode) {
   constexpr int kRed = 4 * NF;
@@ -89,8 +92,8 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
       pan[NF * k + 4] = v;
     }
   }
-  double2* rc = pan + synth_pan_slots(N, NF);  // OTF: [L] (a(l,m), a(l,m) / a(l-1,m))
-  if (OTF) {
+  double2* rc = pan + synth_pan_slots(N, NF);  // [L] (a(l,m), a(l,m) / a(l-1,m))
+  {
     for (int k = threadIdx.x; k < L + kOtfBatch; k += blockDim.x) {
       const int l = m + k;
       double2 c = make_double2(0.0, 0.0);
@@ -105,6 +108,29 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
     }
   }
   __syncthreads();
+  // FP32 products read the panel as float2, rounded once per entry and written
+  // in place over the front of the FP64 panel (every entry is read into
+  // registers before any is overwritten); the padding entries become zero
+  using TT2 = typename std::conditional<std::is_same<TT, float>::value, float2, double2>::type;
+  if (std::is_same<TT, float>::value) {
+    constexpr int kPer = kPanelConvPerThread;
+    const int npan = NF * (L + kOtfBatch);
+    double2 v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = threadIdx.x + i * kSynthThreads;
+      v[i] = (e < NF * L) ? pan[e] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    float2* pf = reinterpret_cast<float2*>(pan);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = threadIdx.x + i * kSynthThreads;
+      if (e < npan) pf[e] = make_float2((float)v[i].x, (float)v[i].y);
+    }
+    __syncthreads();
+  }
+  const TT2* pt = reinterpret_cast<const TT2*>(pan);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -118,7 +144,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int i = 0; i < kRed; ++i) acc[r][i] = TT(0);
-  if (OTF && k0 < k1) {
+  if (k0 < k1) {
     // seeds: the table rows k0 and k0 + 1 (k0 even), then the recurrence
     const double* t = g.T1 + t1_order_offset(N, m, nh);
     double P2[R], P1[R], x[R];
@@ -134,14 +160,16 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const double2 A0 = pan[NF * k0 + f];
-      const double2 A1 = (k0 + 1 < k1) ? pan[NF * (k0 + 1) + f] : make_double2(0.0, 0.0);
+      const TT2 A0 = pt[NF * k0 + f];
+      TT2 A1 = pt[NF * k0 + f];
+      if (k0 + 1 < k1) A1 = pt[NF * (k0 + 1) + f];
+      else A1.x = A1.y = TT(0);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        acc[r][4 * f + 0] = fma((TT)P2[r], (TT)A0.x, acc[r][4 * f + 0]);
-        acc[r][4 * f + 1] = fma((TT)P2[r], (TT)A0.y, acc[r][4 * f + 1]);
-        acc[r][4 * f + 2] = fma((TT)P1[r], (TT)A1.x, acc[r][4 * f + 2]);
-        acc[r][4 * f + 3] = fma((TT)P1[r], (TT)A1.y, acc[r][4 * f + 3]);
+        acc[r][4 * f + 0] = fma((TT)P2[r], A0.x, acc[r][4 * f + 0]);
+        acc[r][4 * f + 1] = fma((TT)P2[r], A0.y, acc[r][4 * f + 1]);
+        acc[r][4 * f + 2] = fma((TT)P1[r], A1.x, acc[r][4 * f + 2]);
+        acc[r][4 * f + 3] = fma((TT)P1[r], A1.y, acc[r][4 * f + 3]);
       }
     }
     // batches of kB degrees: the batch's coefficient pairs and panel entries are
@@ -149,12 +177,13 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
     // latitude of the lane and the products are accumulated (entries past k1
     // are padding and are not accumulated)
     for (int kb = k0 + 2; kb < k1; kb += kB) {
-      double2 c[kB], A[kB][NF];
+      double2 c[kB];
+      TT2 A[kB][NF];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         c[u] = rc[kb + u];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) A[u][f] = pan[NF * (kb + u) + f];
+        for (int f = 0; f < NF; ++f) A[u][f] = pt[NF * (kb + u) + f];
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -169,43 +198,12 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
         for (int u = 0; u < kB; ++u) {
           if (kb + u < k1) {
             const int par = (u & 1) * 2;  // kb is even
+            const TT vt = (TT)v[u];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-              acc[r][4 * f + par + 0] = fma((TT)v[u], (TT)A[u][f].x, acc[r][4 * f + par + 0]);
-              acc[r][4 * f + par + 1] = fma((TT)v[u], (TT)A[u][f].y, acc[r][4 * f + par + 1]);
+              acc[r][4 * f + par + 0] = fma(vt, A[u][f].x, acc[r][4 * f + par + 0]);
+              acc[r][4 * f + par + 1] = fma(vt, A[u][f].y, acc[r][4 * f + par + 1]);
             }
-          }
-        }
-      }
-    }
-  }
-  if (!OTF && pbase < nh && k0 < k1) {
-    const int p = pbase;
-    const TT* t = synthesis_table<TT>(g) + t1_order_offset(N, m, nh) + p;
-    // batches of kBatch degrees; the next batch's table loads are issued before
-    // the current batch's FMAs so that 2 kBatch loads are in flight
-    TT tn[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) tn[u] = (k0 + u < k1) ? t[(int64_t)(k0 + u) * nh] : TT(0);
-    for (int kb = k0; kb < k1; kb += kBatch) {
-      TT tc[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) tc[u] = tn[u];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int k = kb + kBatch + u;
-        tn[u] = (k < k1) ? t[(int64_t)k * nh] : TT(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int k = kb + u;
-        if (k < k1) {
-          const int par = (u & 1) * 2;  // kb and k0 are even: parity of k is that of u
-#pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            const double2 A = pan[NF * k + f];
-            acc[0][4 * f + par + 0] = fma(tc[u], (TT)A.x, acc[0][4 * f + par + 0]);
-            acc[0][4 * f + par + 1] = fma(tc[u], (TT)A.y, acc[0][4 * f + par + 1]);
           }
         }
       }
@@ -456,35 +454,45 @@ size_t synthesis_adv_lds_bytes(int N) {
   return sizeof(double2) * (size_t)(arrays > red ? arrays : red);
 }
 
+// Four-field recurrence synthesis with TT products: one to three latitudes per
+// lane by grid size (measured best: R = 3 at nh = 384, R = 1 at nh <= 192, where
+// the grid has too few tiles for more).
+template <typename TT>
+hipError_t launch_synthesis_otf4(const GroupView& g, const SynthInput& in, int mode,
+                                 hipStream_t s) {
+  dim3 block(kSynthThreads);
+  const size_t lds = synthesis_lds_bytes(g.N, 4);
+  if (g.nh >= 384 && g.nh % 192 == 0) {
+    dim3 grid3((g.N + 1) * (g.nh / 192), g.nb);
+    hipLaunchKernelGGL((k_synthesis<TT, 4, 3>), grid3, block, lds, s, g, in, mode);
+  } else if (g.nh >= 256) {
+    dim3 grid2((g.N + 1) * ((g.nh + 127) / 128), g.nb);
+    hipLaunchKernelGGL((k_synthesis<TT, 4, 2>), grid2, block, lds, s, g, in, mode);
+  } else {
+    dim3 grid((g.N + 1) * ((g.nh + 63) / 64), g.nb);
+    hipLaunchKernelGGL((k_synthesis<TT, 4>), grid, block, lds, s, g, in, mode);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, hipStream_t s) {
   dim3 block(kSynthThreads);
   const int ntile = (g.nh + 63) / 64;
   dim3 grid((g.N + 1) * ntile, g.nb);
   if (mode == SYNTH_ADJ)
-    hipLaunchKernelGGL((k_synthesis<double, 5, true>), grid, block,
-                       synthesis_lds_bytes(g.N, 5, true), s, g, in, mode);
-  else if (g.precision == NSE_PREC_FP32)
-    hipLaunchKernelGGL((k_synthesis<float, 4>), grid, block, synthesis_lds_bytes(g.N, 4), s, g,
-                       in, mode);
-  else if (mode == SYNTH_NONLINEAR && g.nh < 256) {
+    hipLaunchKernelGGL((k_synthesis<double, 5>), grid, block,
+                       synthesis_lds_bytes(g.N, 5), s, g, in, mode);
+  else if (g.precision == NSE_PREC_FP32) {
+    if (4 * (g.N + 2 + kOtfBatch) > kPanelConvPerThread * kSynthThreads) return hipErrorInvalidValue;
+    return launch_synthesis_otf4<float>(g, in, mode, s);
+  } else if (mode == SYNTH_NONLINEAR && g.nh < 256) {
     // one latitude per lane: the loop is bound by the LDS reads, and the
     // derivative-on-Legendre form reads three values per degree instead of five
     // (T255: 14.2 -> 13.8 us); with two or three latitudes per lane the panel
     // form's fewer FMAs per latitude win (T511: 38.6 us against 44.4 us)
     hipLaunchKernelGGL(k_synthesis_adv<1>, grid, block, synthesis_adv_lds_bytes(g.N), s, g, in);
-  } else if (g.nh >= 384 && g.nh % 192 == 0) {
-    // large grids: three latitudes per lane (measured best at nh = 384; at
-    // nh <= 192 one latitude per lane is faster, the grid having too few tiles)
-    dim3 grid3((g.N + 1) * (g.nh / 192), g.nb);
-    hipLaunchKernelGGL((k_synthesis<double, 4, true, 3>), grid3, block,
-                       synthesis_lds_bytes(g.N, 4, true), s, g, in, mode);
-  } else if (g.nh >= 256) {
-    dim3 grid2((g.N + 1) * ((g.nh + 127) / 128), g.nb);
-    hipLaunchKernelGGL((k_synthesis<double, 4, true, 2>), grid2, block,
-                       synthesis_lds_bytes(g.N, 4, true), s, g, in, mode);
   } else {
-    hipLaunchKernelGGL((k_synthesis<double, 4, true>), grid, block,
-                       synthesis_lds_bytes(g.N, 4, true), s, g, in, mode);
+    return launch_synthesis_otf4<double>(g, in, mode, s);
   }
   return hipGetLastError();
 }

@@ -39,8 +39,11 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("N", [15, 31, 255, 511])
+# N = 400 runs on its default grid of 625 latitudes (313 northern, the middle one on
+# the equator): the FP32 recurrence kernels with two latitudes per lane in the
+# synthesis and five in the analysis
+@pytest.mark.parametrize("prec,N", [(p, n) for p in ("fp32", "bf16x3") for n in (15, 31, 255, 511)]
+                         + [("fp32", 400)])
 def test_nonlinear_reduced_precision_vs_oracle(prec, N):
     _say(f"case: nonlinear {prec} N={N}")
     s = pkg.Sphere([(N, 0, 1e-5)], omega=OMEGA, dt=1e-3, precision=prec)
