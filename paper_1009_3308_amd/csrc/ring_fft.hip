@@ -279,24 +279,6 @@ __device__ __forceinline__ void fft_any(double2* x0, double2* x1, const FftPlan&
   }
 }
 
-// Spectrum of the field pair (a, b) of one ring into x[0..M):
-// x_m = G^a_m + i G^b_m, x_{M-m} = conj(G^a_m) + i conj(G^b_m), zero elsewhere.
-// G[m] is read from F[f][m][lat] (stride nlat between orders).
-__device__ void load_pair(double2* x, const double2* __restrict__ Fa,
-                          const double2* __restrict__ Fb, int lat, int N, int M, int nlat) {
-  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
-    const double2 ga = Fa[(int64_t)m * nlat + lat];
-    const double2 gb = Fb[(int64_t)m * nlat + lat];
-    if (m == 0) {
-      x[0] = make_double2(ga.x, gb.x);
-    } else {
-      x[pad(m)] = make_double2(ga.x - gb.y, ga.y + gb.x);        // ga + i gb
-      x[pad(M - m)] = make_double2(ga.x + gb.y, -ga.y + gb.x);   // conj(ga) + i conj(gb)
-    }
-  }
-  for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
-}
-
 // Spectrum of one real field, G[m] (read from F[f][m][lat]) for m >= 1 scaled
 // by s1: x_0 = Re G_0, x_m = s1 G_m, x_{M-m} = s1 conj(G_m), zero elsewhere.
 __device__ void load_single(double2* x, const double2* __restrict__ G, double s1, int lat, int N,
@@ -311,6 +293,65 @@ __device__ void load_single(double2* x, const double2* __restrict__ G, double s1
     }
   }
   for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
+}
+
+// The ring's inputs for the forward kernel: the twiddle half table into tw and
+// the spectra of two field pairs into x0 = (Fa0, Fb0) and x1 = (Fa1, Fb1): for a
+// pair (a, b), x_m = G^a_m + i G^b_m, x_{M-m} = conj(G^a_m) + i conj(G^b_m) and
+// zero elsewhere, G[m] read from F[f][m][lat] (stride nlat between orders).
+// Every global load is issued before the first LDS write
+// (one memory round trip for the ring instead of one per array); thread t
+// loads order m = t mod (N+1) of pair t / (N+1). Since 3N + 2 <= M <= MAXM,
+// 2 (N+1) <= 2 (MAXM / 3 + 1) <= KI NT.
+template <int MAXM, int NT>
+__device__ void load_ring(double2* x0, double2* x1, double2* tw, const double2* __restrict__ gtw,
+                          const double2* __restrict__ Fa0, const double2* __restrict__ Fb0,
+                          const double2* __restrict__ Fa1, const double2* __restrict__ Fb1,
+                          int lat, int N, int M, int nlat) {
+  constexpr int KI = (2 * (MAXM / 3 + 1) + NT - 1) / NT;
+  constexpr int KT = (MAXM / 2 + NT - 1) / NT;
+  const int n1 = N + 1;
+  double2 ga[KI], gb[KI], t[KT];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    ga[i] = gb[i] = make_double2(0.0, 0.0);
+    if (idx < 2 * n1) {
+      const bool second = idx >= n1;
+      const int64_t off = (int64_t)(idx - (second ? n1 : 0)) * nlat + lat;
+      ga[i] = (second ? Fa1 : Fa0)[off];
+      gb[i] = (second ? Fb1 : Fb0)[off];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) t[i] = gtw[j];
+  }
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) tw[j] = t[i];
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx < 2 * n1) {
+      const bool second = idx >= n1;
+      const int m = idx - (second ? n1 : 0);
+      double2* x = second ? x1 : x0;
+      if (m == 0) {
+        x[0] = make_double2(ga[i].x, gb[i].x);
+      } else {
+        x[pad(m)] = make_double2(ga[i].x - gb[i].y, ga[i].y + gb[i].x);       // ga + i gb
+        x[pad(M - m)] = make_double2(ga[i].x + gb[i].y, -ga[i].y + gb[i].x);  // conj(ga) + i conj(gb)
+      }
+    }
+  }
+  for (int j = N + 1 + threadIdx.x; j < M - N; j += NT) {
+    x0[pad(j)] = make_double2(0.0, 0.0);
+    x1[pad(j)] = make_double2(0.0, 0.0);
+  }
 }
 
 }  // namespace
@@ -335,7 +376,6 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   double2* A0 = lds;
   double2* A1 = lds + PL;
   double2* tw = lds + 2 * PL;
-  for (int j = threadIdx.x; j < M / 2; j += blockDim.x) tw[j] = g.tw[j];
   const double x = g.mu[p];
   const double sin2 = (1.0 - x) * (1.0 + x);
   const int64_t fstride = (int64_t)(N + 1) * nlat;
@@ -344,8 +384,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   if (mode == SYNTH_GRID) {
     // u_theta = f0 / sin, u_phi = -f1 / sin, zeta = f2
     const double rs = 1.0 / sqrt(sin2);
-    load_pair(A0, F0, F0 + fstride, lat, N, M, nlat);
-    load_pair(A1, F0 + 2 * fstride, F0 + 2 * fstride, lat, N, M, nlat);
+    load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + fstride, F0 + 2 * fstride, F0 + 2 * fstride,
+                        lat, N, M, nlat);
     __syncthreads();
     fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
     double* g0 = grid_out + ((int64_t)0 * nlat + lat) * M;
@@ -361,8 +401,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   }
 
   // inverse transforms of f0 + i f2 and f1 + i f3
-  load_pair(A0, F0, F0 + 2 * fstride, lat, N, M, nlat);
-  load_pair(A1, F0 + fstride, F0 + 3 * fstride, lat, N, M, nlat);
+  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + 2 * fstride, F0 + fstride, F0 + 3 * fstride, lat,
+                      N, M, nlat);
   __syncthreads();
   fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   const double inv_sin2 = 1.0 / sin2;
@@ -415,15 +455,14 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   double2* A0 = lds;
   double2* A1 = lds + PL;
   double2* tw = lds + 2 * PL;
-  for (int j = threadIdx.x; j < M / 2; j += blockDim.x) tw[j] = g.tw[j];
   const double x = g.mu[p];
   const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
   const int64_t fstride = (int64_t)(N + 1) * nlat;
   const double2* F5 = g.Fa + (int64_t)b * 5 * fstride;
 
   // forward grid fields of this ring
-  load_pair(A0, F5, F5 + 2 * fstride, lat, N, M, nlat);
-  load_pair(A1, F5 + fstride, F5 + 3 * fstride, lat, N, M, nlat);
+  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F5, F5 + 2 * fstride, F5 + fstride, F5 + 3 * fstride, lat,
+                      N, M, nlat);
   __syncthreads();
   fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   double g0[PTS], g1[PTS], g2[PTS], g3[PTS];

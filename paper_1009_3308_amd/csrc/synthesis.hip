@@ -347,6 +347,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int i = 0; i < kRed; ++i) acc[r][i] = 0.0;
+  double XP1[R];  // mu Pbar at the newest degree
+#pragma unroll
+  for (int r = 0; r < R; ++r) XP1[r] = x[r] * P1[r];
   if (k0 < k1) {
     {
       // degree k0 (even): Pbar terms to the even part, D terms to the odd part
@@ -395,13 +398,16 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
       for (int r = 0; r < R; ++r) {
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
-          const double v = fma(c[u].x * x[r], P1[r], -c[u].y * P2[r]);
+          // mu Pbar[l] serves both this degree's D and the next recurrence step
+          const double v = fma(c[u].x, XP1[r], -c[u].y * P2[r]);
+          const double xv = x[r] * v;
           P2[r] = P1[r];
           P1[r] = v;
+          XP1[r] = xv;
           if (kb + u < k1) {
             const int qp = 2 * ((u + 1) & 1);  // part of the Pbar terms
             const int qd = 2 - qp;             // part of the D terms
-            const double D = fma((dl0 + u) * x[r], v, -d[u].x * P2[r]);
+            const double D = fma(dl0 + u, xv, -d[u].x * P2[r]);
             acc[r][0 + qp] = fma(v, ps[u].x, acc[r][0 + qp]);
             acc[r][1 + qp] = fma(v, ps[u].y, acc[r][1 + qp]);
             acc[r][4 + qd] = fma(D, ps[u].x, acc[r][4 + qd]);
