@@ -79,13 +79,20 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     }
   }
   // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p');
-  // the thread's first pair is requested before the coefficient pairs are
-  // computed, so that their square roots overlap its latency
+  // all of the thread's pairs (p = t and t + 256; nh <= kMaxM / 4 = 384) are
+  // requested before the coefficient pairs are computed, so that their square
+  // roots and the LDS writes wait for one memory round trip
+  static_assert(kMaxM / 4 <= 2 * kAnalThreads, "two ring pairs per thread");
   const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
-  double2 qn = make_double2(0.0, 0.0), qs = qn;
-  if ((int)threadIdx.x < nh) {
-    qn = Wb[(int64_t)threadIdx.x * (N + 1)];
-    qs = Wb[(int64_t)(g.nlat - 1 - (int)threadIdx.x) * (N + 1)];
+  double2 qn[2], qs[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int p = threadIdx.x + i * kAnalThreads;
+    qn[i] = qs[i] = make_double2(0.0, 0.0);
+    if (p < nh) {
+      qn[i] = Wb[(int64_t)p * (N + 1)];
+      qs[i] = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+    }
   }
   // recurrence pairs of the tile's degrees (k >= 2 of the order)
   if (threadIdx.x < 64) {
@@ -100,13 +107,13 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     }
     rc[threadIdx.x] = c;
   }
-  for (int p = threadIdx.x; p < nh; p += blockDim.x) {
-    if (p != (int)threadIdx.x) {
-      qn = Wb[(int64_t)p * (N + 1)];
-      qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int p = threadIdx.x + i * kAnalThreads;
+    if (p < nh) {
+      wsh[p] = make_double2(qn[i].x + qs[i].x, qn[i].y + qs[i].y);
+      wsh[nh + p] = make_double2(qn[i].x - qs[i].x, qn[i].y - qs[i].y);
     }
-    wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
-    wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
   }
   __syncthreads();
   if (!active) return;

@@ -279,22 +279,6 @@ __device__ __forceinline__ void fft_any(double2* x0, double2* x1, const FftPlan&
   }
 }
 
-// Spectrum of one real field, G[m] (read from F[f][m][lat]) for m >= 1 scaled
-// by s1: x_0 = Re G_0, x_m = s1 G_m, x_{M-m} = s1 conj(G_m), zero elsewhere.
-__device__ void load_single(double2* x, const double2* __restrict__ G, double s1, int lat, int N,
-                            int M, int nlat) {
-  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
-    const double2 v = G[(int64_t)m * nlat + lat];
-    if (m == 0) {
-      x[0] = make_double2(v.x, 0.0);
-    } else {
-      x[pad(m)] = make_double2(s1 * v.x, s1 * v.y);
-      x[pad(M - m)] = make_double2(s1 * v.x, -s1 * v.y);
-    }
-  }
-  for (int j = N + 1 + threadIdx.x; j < M - N; j += blockDim.x) x[pad(j)] = make_double2(0.0, 0.0);
-}
-
 // The ring's inputs for the forward kernel: the twiddle half table into tw and
 // the spectra of two field pairs into x0 = (Fa0, Fb0) and x1 = (Fa1, Fb1): for a
 // pair (a, b), x_m = G^a_m + i G^b_m, x_{M-m} = conj(G^a_m) + i conj(G^b_m) and
@@ -460,6 +444,15 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   const int64_t fstride = (int64_t)(N + 1) * nlat;
   const double2* F5 = g.Fa + (int64_t)b * 5 * fstride;
 
+  // the ring's fifth field (the cotangent of its spectrum Q), requested now and
+  // written to LDS after the forward transforms; 3N + 2 <= M <= MAXM bounds N + 1
+  constexpr int KS = (MAXM / 3 + 1 + NT - 1) / NT;
+  double2 qbar[KS];
+#pragma unroll
+  for (int i = 0; i < KS; ++i) {
+    const int m = threadIdx.x + i * NT;
+    qbar[i] = (m <= N) ? F5[4 * fstride + (int64_t)m * nlat + lat] : make_double2(0.0, 0.0);
+  }
   // forward grid fields of this ring
   load_ring<MAXM, NT>(A0, A1, tw, g.tw, F5, F5 + 2 * fstride, F5 + fstride, F5 + 3 * fstride, lat,
                       N, M, nlat);
@@ -479,8 +472,19 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
     }
   }
   __syncthreads();
-  // cotangent of the grid product
-  load_single(A0, F5 + 4 * fstride, 0.5, lat, N, M, nlat);
+  // cotangent of the grid product: the real field of spectrum Qbar / 2 (m >= 1),
+  // x_0 = Re Qbar_0, x_m = Qbar_m / 2, x_{M-m} = conj(Qbar_m) / 2, zero elsewhere
+#pragma unroll
+  for (int i = 0; i < KS; ++i) {
+    const int m = threadIdx.x + i * NT;
+    if (m == 0) {
+      A0[0] = make_double2(qbar[i].x, 0.0);
+    } else if (m <= N) {
+      A0[pad(m)] = make_double2(0.5 * qbar[i].x, 0.5 * qbar[i].y);
+      A0[pad(M - m)] = make_double2(0.5 * qbar[i].x, -0.5 * qbar[i].y);
+    }
+  }
+  for (int j = N + 1 + threadIdx.x; j < M - N; j += NT) A0[pad(j)] = make_double2(0.0, 0.0);
   __syncthreads();
   fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
   const double clat = (6.283185307179586477 / M) * g.w[p];
