@@ -32,14 +32,16 @@ size_t synthesis_adjoint_lds_bytes(int nh) {
 
 // One workgroup of four waves per (order m, tile of 64 degrees k < N+2-m,
 // member); one thread per degree, each wave summing a quarter of the northern
-// latitudes of T2[m][tile][p][64].
+// latitudes of T2[m][tile][p][64]. Orders are taken in XCD-local chunks of four
+// neighbouring m so that the strided reads of Fbar[lat][m] share L2 lines.
 __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) {
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (N + 2 + 63) / 64;
-  const int m = blockIdx.x / ntile;
-  const int tile = blockIdx.x - m * ntile;
+  const int item = xcd_item(blockIdx.x, 4 * ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
   const int L = N + 2 - m;
-  if (tile * 64 >= L) return;  // uniform across the workgroup
+  if (m > N || tile * 64 >= L) return;  // uniform across the workgroup
   const int b = blockIdx.y;
   extern __shared__ double2 fsh[];  // [f][parity][nh]
   const int64_t fstride = (int64_t)(N + 1) * nlat;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void k_prep_adjoint(GroupView g, double2* alph
 
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s) {
   const int ntile = (g.N + 2 + 63) / 64;
-  dim3 grid((g.N + 1) * ntile, g.nb);
+  dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
   hipLaunchKernelGGL(k_synthesis_adjoint, grid, dim3(kAdjThreads),
                      synthesis_adjoint_lds_bytes(g.nh), s, g);
   return hipGetLastError();

@@ -431,7 +431,8 @@ template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   constexpr int PTS = (MAXM + NT - 1) / NT;
   const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
-  const int lat = blockIdx.x;
+  const int lat = xcd_item(blockIdx.x, 8);  // XCD-local chunks of 8 rings share L2 lines of Fa
+  if (lat >= nlat) return;
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;
   const int PL = padded_len(M);
@@ -535,7 +536,8 @@ template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
                                                      const double* __restrict__ u_grid) {
   const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
-  const int lat = blockIdx.x;
+  const int lat = xcd_item(blockIdx.x, 8);
+  if (lat >= g.nlat) return;
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;
   const int PL = padded_len(M);
@@ -586,7 +588,7 @@ hipError_t ring_dispatch(int M, F&& launch) {
 }
 
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
-  dim3 grid(g.nlat, g.nb);
+  dim3 grid(xcd_grid(g.nlat, 8), g.nb);
   const size_t lds = ring_lds_bytes(g.M);
   return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
     constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
@@ -597,7 +599,7 @@ hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStrea
 
 hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const double* u_grid,
                                hipStream_t s) {
-  dim3 grid(g.nlat, g.nb);
+  dim3 grid(xcd_grid(g.nlat, 8), g.nb);
   const size_t lds = ring_lds_bytes(g.M);
   return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
     constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
