@@ -15,6 +15,7 @@
 //   zeta_bar[j] = -i m f3_bar[j] + cm(j+1) f2_bar[j+1] - cp(j-1) f2_bar[j-1],
 //   alpha_bar[j] = lambda^(-1/2) psi_bar[j] + lambda^(1/2) zeta_bar[j],
 // zero at l = 0 and real at m = 0 (those inputs are fixed to zero).
+#include "lane_ops.h"
 #include "spectral_ops.h"
 
 namespace nse {
@@ -156,11 +157,150 @@ __global__ __launch_bounds__(256) void k_prep_adjoint(GroupView g, double2* alph
     alpha_bar[g.off[b] + coeff_offset(N, m) + k] = alpha_bar_at(g, P, m, k);
 }
 
+// The same sums with the Legendre values continued in registers instead of
+// streamed from T2 (grids with nh <= 64 R, R <= 3 latitudes per lane). As in the
+// recurrence analysis of the forward path, wave w of the (m, 64-degree tile)
+// workgroup owns the degrees 16 w .. 16 w + 15 of the tile and its lanes are
+// latitudes; each lane seeds the recurrence of eq. (sph_har) from the T1 rows of
+// the wave's first two degrees and keeps the sixteen values of each of its
+// latitudes in registers. Then, field by field, it multiplies them by its
+// latitudes' folded cotangents (even or odd part by the parity of k) and the
+// sixteen complex sums are formed across the lanes by the register butterfly,
+// which leaves degree 8 b5 + 4 b4 + 2 b3 + b2 of the wave's block (b = lane bits)
+// in the lanes with b1 = b0 = 0.
+template <int R>
+__global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint_otf(GroupView g) {
+  constexpr int kDeg = kButterfly;  // degrees per wave
+  const int N = g.N, nh = g.nh, nlat = g.nlat;
+  const int ntile = (N + 2 + 63) / 64;
+  const int item = xcd_item(blockIdx.x, 4 * ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
+  const int L = N + 2 - m;  // k < L; T1 holds the rows k = 0 .. L - 1 of order m
+  if (m > N || tile * 64 >= L) return;  // uniform across the workgroup
+  const int b = blockIdx.y;
+  extern __shared__ double2 fsh[];  // [f][parity][nh], then the tile's recurrence pairs [64]
+  double2* rc = fsh + 8 * nh;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kt = tile * 64;
+  const int j0 = wave * kDeg;
+  const bool active = kt + j0 < L;
+  // seeds first, their latency overlapping the fold
+  double x[R], P1[R], P2[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = P1[r] = P2[r] = 0.0;
+  if (active) {
+    const double* t = g.T1 + t1_order_offset(N, m, nh) + (int64_t)(kt + j0) * nh;
+    const bool second = kt + j0 + 1 < L;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = lane + 64 * r;
+      if (p < nh) {
+        P2[r] = t[p];
+        if (second) P1[r] = t[nh + p];
+        x[r] = g.mu[p];
+      }
+    }
+  }
+  // the cotangents of the four fields at every latitude pair (4 nh <= 256 R items,
+  // R per thread), all requested before the first LDS write
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + m;  // Fbar[b][f][lat][m]
+  double2 gn[R], gs[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int idx = threadIdx.x + i * kAdjThreads;
+    gn[i] = gs[i] = make_double2(0.0, 0.0);
+    if (idx < 4 * nh) {
+      const int f = idx / nh, p = idx - f * nh;
+      const int ps = nlat - 1 - p;
+      gn[i] = Gb[f * fstride + (int64_t)p * (N + 1)];
+      if (ps != p) gs[i] = Gb[f * fstride + (int64_t)ps * (N + 1)];
+    }
+  }
+  // recurrence pairs (a(l,m), a(l,m) / a(l-1,m)) of the tile's degrees k = 2 .. L - 1;
+  // zero elsewhere, so the values past the order's last degree stay zero
+  if (threadIdx.x < 64) {
+    const int k = kt + threadIdx.x;
+    double2 c = make_double2(0.0, 0.0);
+    if (k >= 2 && k < L) {
+      const double dl = (double)(m + k), dm = (double)m;
+      const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+      const double al1 =
+          sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
+      c = make_double2(al, al / al1);
+    }
+    rc[threadIdx.x] = c;
+  }
+  // fold: We = G(p) + G(p'), Wo = G(p) - G(p') (the equator ring of an odd rule,
+  // its own mirror, counted once: gs = 0)
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int idx = threadIdx.x + i * kAdjThreads;
+    if (idx < 4 * nh) {
+      const int f = idx / nh, p = idx - f * nh;
+      fsh[(2 * f) * nh + p] = make_double2(gn[i].x + gs[i].x, gn[i].y + gs[i].y);
+      fsh[(2 * f + 1) * nh + p] = make_double2(gn[i].x - gs[i].x, gn[i].y - gs[i].y);
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  double v[kDeg][R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    v[0][r] = P2[r];
+    v[1][r] = P1[r];
+  }
+#pragma unroll
+  for (int i = 2; i < kDeg; ++i) {
+    const double2 c = rc[j0 + i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i][r] = fma(c.x * x[r], v[i - 1][r], -c.y * v[i - 2][r]);
+  }
+  const int j = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) +
+                ((lane >> 2) & 1);
+  const int k = kt + j0 + j;
+  double2* out = g.Pbar + (((int64_t)b * (N + 1) + m) * (N + 2) + k) * 4;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double sr[kDeg], si[kDeg];
+#pragma unroll
+    for (int i = 0; i < kDeg; ++i) sr[i] = si[i] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = lane + 64 * r;
+      double2 we = make_double2(0.0, 0.0), wo = we;
+      if (p < nh) {
+        we = fsh[(2 * f) * nh + p];
+        wo = fsh[(2 * f + 1) * nh + p];
+      }
+#pragma unroll
+      for (int i = 0; i < kDeg; ++i) {
+        const double2 w = (i & 1) ? wo : we;  // kt and j0 are even: the parity of k is that of i
+        sr[i] = fma(v[i][r], w.x, sr[i]);
+        si[i] = fma(v[i][r], w.y, si[i]);
+      }
+    }
+    lane_butterfly16(sr, si, lane);
+    if ((lane & 3) == 0 && k < L) out[f] = make_double2(sr[0], si[0]);
+  }
+}
+
+size_t synthesis_adjoint_otf_lds_bytes(int nh) { return sizeof(double2) * (size_t)(8 * nh + 64); }
+
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s) {
   const int ntile = (g.N + 2 + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
-  hipLaunchKernelGGL(k_synthesis_adjoint, grid, dim3(kAdjThreads),
-                     synthesis_adjoint_lds_bytes(g.nh), s, g);
+  const size_t lds = synthesis_adjoint_otf_lds_bytes(g.nh);
+  switch ((g.nh + 63) / 64) {
+    case 1: hipLaunchKernelGGL(k_synthesis_adjoint_otf<1>, grid, dim3(kAdjThreads), lds, s, g); break;
+    case 2: hipLaunchKernelGGL(k_synthesis_adjoint_otf<2>, grid, dim3(kAdjThreads), lds, s, g); break;
+    case 3: hipLaunchKernelGGL(k_synthesis_adjoint_otf<3>, grid, dim3(kAdjThreads), lds, s, g); break;
+    default:
+      hipLaunchKernelGGL(k_synthesis_adjoint, grid, dim3(kAdjThreads),
+                         synthesis_adjoint_lds_bytes(g.nh), s, g);
+      break;
+  }
   return hipGetLastError();
 }
 
