@@ -58,7 +58,9 @@ def oracle_vjp(N, nlat, alpha, n_bar):
     return g.numpy()
 
 
-@pytest.mark.parametrize("N,nlat", [(7, 0), (31, 0), (29, 45), (31, 50), (63, 0)])
+# (85, 135): 68 northern latitudes, the equator among them, two per lane in the
+# recurrence form of the unweighted analysis
+@pytest.mark.parametrize("N,nlat", [(7, 0), (31, 0), (29, 45), (31, 50), (63, 0), (85, 135)])
 def test_nonlinear_adjoint_vs_oracle_autograd(N, nlat):
     _say(f"case: nonlinear adjoint N={N} nlat={nlat}")
     s = pkg.Sphere([(N, nlat, 1e-3)], omega=OMEGA, dt=1e-3)
@@ -71,10 +73,14 @@ def test_nonlinear_adjoint_vs_oracle_autograd(N, nlat):
     s.close()
 
 
-@pytest.mark.parametrize("N", [255, 511])
-def test_nonlinear_adjoint_dot_product(N):
-    _say(f"case: adjoint dot product N={N}")
-    s = pkg.Sphere([(N, 0, 1e-5)], omega=OMEGA, dt=1e-3)
+# the unweighted analysis of the adjoint keeps its Legendre values in registers
+# for one to three latitudes per lane (127: 96 northern latitudes, two per lane;
+# (140, 225): 113 with the equator; 255: 192, three) and streams the table beyond
+# (511: 384)
+@pytest.mark.parametrize("N,nlat", [(127, 0), (140, 225), (255, 0), (511, 0)])
+def test_nonlinear_adjoint_dot_product(N, nlat):
+    _say(f"case: adjoint dot product N={N} nlat={nlat}")
+    s = pkg.Sphere([(N, nlat, 1e-5)], omega=OMEGA, dt=1e-3)
     a = pkg.to_device(I.initial_state(N))
     d = pkg.to_device(I.directions(N, 1)[0])
     nb = I.cotangent(N)
