@@ -222,15 +222,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint_otf(GroupView
   // zero elsewhere, so the values past the order's last degree stay zero
   if (threadIdx.x < 64) {
     const int k = kt + threadIdx.x;
-    double2 c = make_double2(0.0, 0.0);
-    if (k >= 2 && k < L) {
-      const double dl = (double)(m + k), dm = (double)m;
-      const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
-      const double al1 =
-          sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
-      c = make_double2(al, al / al1);
-    }
-    rc[threadIdx.x] = c;
+    rc[threadIdx.x] = (k >= 2 && k < L) ? g.rec_a[rec_slot(N, m + k, m)] : make_double2(0.0, 0.0);
   }
   // fold: We = G(p) + G(p'), Wo = G(p) - G(p') (the equator ring of an odd rule,
   // its own mirror, counted once: gs = 0)

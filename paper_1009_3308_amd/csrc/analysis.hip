@@ -94,18 +94,12 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       qs[i] = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
     }
   }
-  // recurrence pairs of the tile's degrees (k >= 2 of the order)
+  // recurrence pairs of the tile's degrees (k >= 2 of the order, from the
+  // group's coefficient table; zero past degree N+1, whose values are not used)
   if (threadIdx.x < 64) {
     const int k = kt + threadIdx.x;
-    double2 c = make_double2(0.0, 0.0);
-    if (k >= 2) {
-      const double dl = (double)(m + k), dm = (double)m;
-      const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
-      const double al1 =
-          sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
-      c = make_double2(al, al / al1);
-    }
-    rc[threadIdx.x] = c;
+    rc[threadIdx.x] = (k >= 2 && k <= N + 1 - m) ? g.rec_a[rec_slot(N, m + k, m)]
+                                                 : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {

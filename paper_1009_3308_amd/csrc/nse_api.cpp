@@ -35,6 +35,7 @@ struct Group {
   double *d_mu = nullptr, *d_w = nullptr, *d_T1 = nullptr, *d_T2 = nullptr;
   float *d_T1f = nullptr, *d_T2f = nullptr;
   int64_t* d_t2off = nullptr;
+  double2 *d_rec_a = nullptr, *d_rec_g = nullptr;  // recurrence coefficients (rec_slot)
   uint64_t* d_lps = nullptr;      // split-bf16 synthesis panels (BF16X3 groups)
   int64_t* d_lpsoff = nullptr;
   int64_t lps_stride = 0;         // per member, 8-byte units
@@ -61,6 +62,8 @@ struct Group {
     g.T1f = d_T1f;
     g.T2f = d_T2f;
     g.t2off = d_t2off;
+    g.rec_a = d_rec_a;
+    g.rec_g = d_rec_g;
     g.F = d_F;
     g.Fa = d_Fa;
     g.Fbar = d_Fbar;
@@ -233,6 +236,8 @@ void free_group(Group& g) {
   (void)hipFree(g.d_T1f);
   (void)hipFree(g.d_T2f);
   (void)hipFree(g.d_t2off);
+  (void)hipFree(g.d_rec_a);
+  (void)hipFree(g.d_rec_g);
   (void)hipFree(g.d_lps);
   (void)hipFree(g.d_lpsoff);
   (void)hipFree(g.d_F);
@@ -279,6 +284,31 @@ nse_status build_group(nse_ctx* c, Group& g) {
                        hipMemcpyHostToDevice));
   NSE_HIP(c, dalloc(&g.d_T1, ts1));
   NSE_HIP(c, dalloc(&g.d_T2, ts2));
+  {
+    // recurrence coefficients, in long double and rounded once
+    const int64_t nrec = (int64_t)(g.N + 2) * (g.N + 3) / 2;
+    std::vector<double2> ra(nrec), rg(nrec);
+    for (int m = 0; m <= g.N; ++m) {
+      const long double lm = m;
+      auto a_of = [&](int l) -> long double {
+        const long double ll = l;
+        return std::sqrt((4.0L * ll * ll - 1.0L) / (ll * ll - lm * lm));
+      };
+      for (int l = m; l <= g.N + 1; ++l) {
+        const int64_t sl = rec_slot(g.N, l, m);
+        const long double al = (l > m) ? a_of(l) : 0.0L;
+        const long double ratio = (l > m + 1) ? al / a_of(l - 1) : 0.0L;
+        const long double gl = (l > m) ? (2.0L * l + 1.0L) / al : 0.0L;
+        const long double rs = (l > 0) ? 1.0L / std::sqrt((long double)l * (l + 1)) : 0.0L;
+        ra[sl] = make_double2((double)al, (double)ratio);
+        rg[sl] = make_double2((double)gl, (double)rs);
+      }
+    }
+    NSE_HIP(c, dalloc(&g.d_rec_a, nrec));
+    NSE_HIP(c, dalloc(&g.d_rec_g, nrec));
+    NSE_HIP(c, hipMemcpy(g.d_rec_a, ra.data(), sizeof(double2) * nrec, hipMemcpyHostToDevice));
+    NSE_HIP(c, hipMemcpy(g.d_rec_g, rg.data(), sizeof(double2) * nrec, hipMemcpyHostToDevice));
+  }
   if (c->params.precision == NSE_PREC_BF16X3) {
     // FP32 copies of the tables, split into bf16 pieces in registers (the FP64
     // and FP32 modes continue the recurrences from FP64 seed rows instead)

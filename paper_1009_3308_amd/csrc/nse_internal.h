@@ -43,6 +43,15 @@ __host__ __device__ inline int xcd_grid(int items, int chunk) {
 __host__ __device__ inline int64_t coeff_offset(int N, int m) {
   return (int64_t)m * (2 * N + 3 - m) / 2;
 }
+// Per-degree coefficients of the normalised Legendre recurrence of eq. (sph_har),
+// computed once per group on the host, for l = m .. N+1 at rec_slot(N, l, m):
+//   rec_a = (a(l,m), a(l,m) / a(l-1,m)),  a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)),
+//   rec_g = ((2l+1) e(l), lambda_l^(-1/2)),  e(l) = 1 / a(l,m),
+// with a(m,m) = e(m) = 0, the ratio 0 for l <= m+1 (it multiplies Pbar[m-1,m] = 0)
+// and lambda^(-1/2) = 0 at l = 0.
+__host__ __device__ inline int64_t rec_slot(int N, int l, int m) {
+  return coeff_offset(N + 1, m) + (l - m);
+}
 // Legendre tables, l = m .. N+1 (L = N + 2 - m degrees for order m, k = l - m):
 //   T1[m][k][p]                        (synthesis; latitude fastest, row stride nh)
 //   T2[m][deg tile][p][64 degrees]     (analysis; ceil(L/64) tiles of 64 degrees,
@@ -68,6 +77,8 @@ struct GroupView {
   const float* T1f;         // FP32 copies (precision modes), may be null
   const float* T2f;
   const int64_t* t2off;     // [N+2] start of order m in T2 (element units)
+  const double2* rec_a;     // [(N+2)(N+3)/2] (a(l,m), a(l,m) / a(l-1,m)), slot rec_slot(N, l, m)
+  const double2* rec_g;     // same slots: ((2l+1) e(l), lambda_l^(-1/2)), see rec_slot
   double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
   double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
   double2* Fbar;            // adjoint: [nb][4][nlat][N+1] cotangents of the field spectra

@@ -28,6 +28,9 @@ constexpr int kOtfBatch = 4;  // degrees per recurrence batch (even)
 // panel entries each thread rounds to FP32 (four fields: N + 2 + kOtfBatch
 // degrees; launch_synthesis rejects larger N)
 constexpr int kPanelConvPerThread = 10;
+// recurrence pairs each thread stages (N + 2 + kOtfBatch entries at most; the
+// LDS bound of the kernels keeps N below 680)
+constexpr int kRcPerThread = 3;
 
 // NF fields: per lane 4 NF partial sums (NF fields x (E, O) x (re, im)).
 // The panel [L][NF] double2 is reused afterwards for the cross-wave reduction.
@@ -73,6 +76,14 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   double2* a = sh;              // [L + 1] state coefficients alpha[l], l = m..N (0 beyond)
   double2* pan = sh + (N + 3);  // [L][NF]
 
+  // recurrence pairs of the order (k = 2 .. L-1, from the group's table),
+  // requested with the input states so that one memory round trip covers both
+  double2 rcv[kRcPerThread];
+#pragma unroll
+  for (int i = 0; i < kRcPerThread; ++i) {
+    const int k = threadIdx.x + i * kSynthThreads;
+    rcv[i] = (k >= 2 && k < L) ? g.rec_a[rec_slot(N, m + k, m)] : make_double2(0.0, 0.0);
+  }
   load_order(a, g, in, b, m, L);
   __syncthreads();
   build_panel<NF>(pan, a, N, m, L, mode, in.coriolis, in.stream != 0);
@@ -92,20 +103,11 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
       pan[NF * k + 4] = v;
     }
   }
-  double2* rc = pan + synth_pan_slots(N, NF);  // [L] (a(l,m), a(l,m) / a(l-1,m))
-  {
-    for (int k = threadIdx.x; k < L + kOtfBatch; k += blockDim.x) {
-      const int l = m + k;
-      double2 c = make_double2(0.0, 0.0);
-      if (k >= 2 && k < L) {
-        const double dl = (double)l, dm = (double)m;
-        const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
-        const double al1 = sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) /
-                                ((dl - 1.0) * (dl - 1.0) - dm * dm));
-        c = make_double2(al, al / al1);
-      }
-      rc[k] = c;
-    }
+  double2* rc = pan + synth_pan_slots(N, NF);  // [L + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
+#pragma unroll
+  for (int i = 0; i < kRcPerThread; ++i) {
+    const int k = threadIdx.x + i * kSynthThreads;
+    if (k < L + kOtfBatch) rc[k] = rcv[i];
   }
   __syncthreads();
   // FP32 products read the panel as float2, rounded once per entry and written
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 //   f0 = i m sum psi[l] Pbar,  f1 = sum psi[l] D,  f2 = sum zeta_a[l] D,  f3 = i m sum zeta_a[l] Pbar
 // over l = m..N, with zeta_a[l] = lambda_l psi[l] plus the Coriolis fold at
 // (1, 0), which only f2 sees (f3 carries the factor m = 0 there). Per degree the
-// loop reads psi[l] and two coefficient pairs from LDS, three reads where the
-// panel form needs five, and D[l] has the parity opposite to Pbar[l,m] under
+// loop reads psi[l], zeta_a[l] and two coefficient pairs from LDS, four reads
+// where the panel form needs five, and D[l] has the parity opposite to Pbar[l,m] under
 // mu -> -mu, so its terms go to the other half of the even/odd split. Tiles,
 // latitudes per lane (R) and the cross-wave sums are those of k_synthesis.
 template <int R>
@@ -264,19 +266,21 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   const int K = N + 1 - m;  // degrees m .. N
   extern __shared__ double2 sh[];
   double2* psi = sh;                        // [K + kOtfBatch] psi[l] = lambda^(-1/2) alpha[l]
-  double2* rc = psi + (N + 1 + kOtfBatch);  // [K + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
-  double2* dc = rc + (N + 1 + kOtfBatch);   // [K + kOtfBatch] ((2l+1) e(l), lambda_l)
+  double2* za = psi + (N + 1 + kOtfBatch);  // [K + kOtfBatch] zeta_a[l] = lambda_l psi[l]
+  double2* rc = za + (N + 1 + kOtfBatch);   // [K + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
+  double2* dc = rc + (N + 1 + kOtfBatch);   // [K + kOtfBatch] ((2l+1) e(l), l)
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform across the wave, so the degree bounds are scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pbase = tile * 64 * R + lane;  // latitude of slot r: pbase + 64 r
   const int chunk = ((K + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
   const int k0 = wave * chunk;  // even
   const int k1 = min(K, k0 + chunk);
-  // The prologue's three latencies overlap: the seed rows and the input states
-  // are requested first, the recurrence coefficients (square roots and
-  // divisions) are computed while they arrive, and psi is formed from the
-  // states directly, so one barrier precedes the loop.
+  // The prologue's latencies overlap: the seed rows, the input states and the
+  // order's recurrence coefficients (computed once per group, rec_slot) are
+  // requested together, and psi and zeta_a are formed from the states directly,
+  // so one barrier precedes the loop.
   // seeds: Pbar at k0 (table row k0) and k0 - 1 (row k0 - 1, zero below m)
   double P1[R], P2[R], x[R];
 #pragma unroll
@@ -293,8 +297,8 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
       }
     }
   }
-  const double dm = (double)m;
   const int64_t base = g.off[b] + coeff_offset(N, m);
+  const int64_t rbase = rec_slot(N, m, m);
   for (int k = threadIdx.x; k < K + kOtfBatch; k += blockDim.x) {
     const int l = m + k;
     // input state alpha[l] = sum_i coef_i src_i[l] (l = 1..N; real at m = 0)
@@ -304,27 +308,10 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
       src[i] = make_double2(0.0, 0.0);
       if (i < in.nsrc && k < K && l >= 1) src[i] = in.src[i][base + k];
     }
-    double2 c = make_double2(0.0, 0.0), d = c;
-    double r = 0.0;
+    double2 c = make_double2(0.0, 0.0), e = c;
     if (k < K) {
-      const double dl = (double)l;
-      const double lam = dl * (dl + 1.0);
-      if (l >= 1) r = 1.0 / sqrt(lam);
-      if (k >= 1) {
-        // a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)) = 1 / e(l); a(l-1,m) is
-        // infinite at k = 1, where the ratio multiplies Pbar[m-1,m] = 0
-        const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
-        double ratio = 0.0;
-        if (k >= 2) {
-          const double al1 =
-              sqrt((4.0 * (dl - 1.0) * (dl - 1.0) - 1.0) / ((dl - 1.0) * (dl - 1.0) - dm * dm));
-          ratio = al / al1;
-        }
-        c = make_double2(al, ratio);
-        d = make_double2((2.0 * dl + 1.0) / al, lam);
-      } else {
-        d = make_double2(0.0, lam);  // e(m) = 0
-      }
+      c = g.rec_a[rbase + k];
+      e = g.rec_g[rbase + k];
     }
     double2 v = make_double2(0.0, 0.0);
 #pragma unroll
@@ -335,9 +322,13 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
       }
     }
     if (m == 0) v.y = 0.0;
-    psi[k] = make_double2(v.x * r, v.y * r);
+    const double dl = (double)l;
+    const double lam = (k < K) ? dl * (dl + 1.0) : 0.0;
+    const double2 ps = make_double2(v.x * e.y, v.y * e.y);
+    psi[k] = ps;
+    za[k] = make_double2(lam * ps.x, lam * ps.y);
     rc[k] = c;
-    dc[k] = d;
+    dc[k] = make_double2(e.x, (k < K) ? dl : 0.0);
   }
   __syncthreads();
 
@@ -353,20 +344,18 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   if (k0 < k1) {
     {
       // degree k0 (even): Pbar terms to the even part, D terms to the odd part
-      const double2 ps = psi[k0], d = dc[k0];
-      const double2 za = make_double2(d.y * ps.x, d.y * ps.y);
-      const double dl = (double)(m + k0);
+      const double2 ps = psi[k0], zz = za[k0], d = dc[k0];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double D = fma(dl * x[r], P1[r], -d.x * P2[r]);
+        const double D = fma(d.y, XP1[r], -d.x * P2[r]);
         acc[r][0] = fma(P1[r], ps.x, acc[r][0]);
         acc[r][1] = fma(P1[r], ps.y, acc[r][1]);
         acc[r][6] = fma(D, ps.x, acc[r][6]);
         acc[r][7] = fma(D, ps.y, acc[r][7]);
-        acc[r][10] = fma(D, za.x, acc[r][10]);
-        acc[r][11] = fma(D, za.y, acc[r][11]);
-        acc[r][12] = fma(P1[r], za.x, acc[r][12]);
-        acc[r][13] = fma(P1[r], za.y, acc[r][13]);
+        acc[r][10] = fma(D, zz.x, acc[r][10]);
+        acc[r][11] = fma(D, zz.y, acc[r][11]);
+        acc[r][12] = fma(P1[r], zz.x, acc[r][12]);
+        acc[r][13] = fma(P1[r], zz.y, acc[r][13]);
       }
     }
     if (m == 0 && k0 == 0 && k1 > 1) {
@@ -383,17 +372,14 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
     // degrees k0 + 1 .. k1 - 1 in batches of kB (kb odd: degree kb + u is odd
     // for even u); entries past k1 are padding and are not accumulated
     for (int kb = k0 + 1; kb < k1; kb += kB) {
-      double2 c[kB], ps[kB], d[kB];
+      double2 c[kB], ps[kB], zz[kB], d[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         c[u] = rc[kb + u];
         ps[u] = psi[kb + u];
+        zz[u] = za[kb + u];
         d[u] = dc[kb + u];
       }
-      double2 za[kB];
-#pragma unroll
-      for (int u = 0; u < kB; ++u) za[u] = make_double2(d[u].y * ps[u].x, d[u].y * ps[u].y);
-      const double dl0 = (double)(m + kb);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -407,15 +393,15 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
           if (kb + u < k1) {
             const int qp = 2 * ((u + 1) & 1);  // part of the Pbar terms
             const int qd = 2 - qp;             // part of the D terms
-            const double D = fma(dl0 + u, xv, -d[u].x * P2[r]);
+            const double D = fma(d[u].y, xv, -d[u].x * P2[r]);
             acc[r][0 + qp] = fma(v, ps[u].x, acc[r][0 + qp]);
             acc[r][1 + qp] = fma(v, ps[u].y, acc[r][1 + qp]);
             acc[r][4 + qd] = fma(D, ps[u].x, acc[r][4 + qd]);
             acc[r][5 + qd] = fma(D, ps[u].y, acc[r][5 + qd]);
-            acc[r][8 + qd] = fma(D, za[u].x, acc[r][8 + qd]);
-            acc[r][9 + qd] = fma(D, za[u].y, acc[r][9 + qd]);
-            acc[r][12 + qp] = fma(v, za[u].x, acc[r][12 + qp]);
-            acc[r][13 + qp] = fma(v, za[u].y, acc[r][13 + qp]);
+            acc[r][8 + qd] = fma(D, zz[u].x, acc[r][8 + qd]);
+            acc[r][9 + qd] = fma(D, zz[u].y, acc[r][9 + qd]);
+            acc[r][12 + qp] = fma(v, zz[u].x, acc[r][12 + qp]);
+            acc[r][13 + qp] = fma(v, zz[u].y, acc[r][13 + qp]);
           }
         }
       }
@@ -423,6 +409,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   }
   // cross-wave sums through LDS (the coefficient arrays are no longer needed);
   // wave w finishes field w of its latitudes; f0 and f3 take the factor i m
+  const double dm = (double)m;
   double* red = reinterpret_cast<double*>(sh);  // [wave][kRed][64]
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -455,7 +442,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
 }
 
 size_t synthesis_adv_lds_bytes(int N) {
-  const int arrays = 3 * (N + 1 + kOtfBatch);
+  const int arrays = 4 * (N + 1 + kOtfBatch);
   const int red = kSynthWaves * 16 * 64 / 2;
   return sizeof(double2) * (size_t)(arrays > red ? arrays : red);
 }
