@@ -55,7 +55,9 @@ def algorithmic_bytes(N, nlat, order, nsrc):
     """HBM bytes each kernel must move per launch (one member). The FP64
     synthesis reads two table rows per wave (four waves per order) and the FP64
     analysis two per 16-degree block of a wave, as seeds of the Legendre
-    recurrence, instead of the table."""
+    recurrence, instead of the table; both read the per-degree recurrence
+    coefficients of the group (two double2 per degree l = m..N for the
+    synthesis, one for the analysis) once."""
     nh = (nlat + 1) // 2
     slots = (N + 1) * (N + 2) // 2
     F = 4 * nlat * (N + 1) * 16
@@ -63,10 +65,11 @@ def algorithmic_bytes(N, nlat, order, nsrc):
     seeds = 8 * 2 * 4 * nh * (N + 1)
     blocks = sum((N + 1 - m + 15) // 16 for m in range(N + 1))
     return {
-        "synthesis": seeds + nsrc * slots * 16 + F,
+        "synthesis": seeds + nsrc * slots * 16 + F + slots * 32,
         "ring": F + W,
-        # two table rows per 16-degree block (recurrence seeds), ring spectra, states
-        "analysis": 8 * 2 * nh * blocks + W + (2 * (order + 1) + 1) * slots * 16,
+        # two table rows per 16-degree block (recurrence seeds), ring spectra, states,
+        # recurrence coefficients
+        "analysis": 8 * 2 * nh * blocks + W + (2 * (order + 1) + 1) * slots * 16 + slots * 16,
     }
 
 

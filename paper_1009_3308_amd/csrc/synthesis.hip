@@ -68,8 +68,12 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (nh + 64 * R - 1) / (64 * R);
-  const int m = blockIdx.x / ntile;
-  const int tile = blockIdx.x - m * ntile;
+  // the tiles of one order run on one XCD and share its L2 for the order's
+  // input states and coefficients
+  const int item = xcd_item(blockIdx.x, ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
+  if (m > N) return;  // uniform across the workgroup
   const int b = blockIdx.y;
   const int L = N + 2 - m;  // degrees m .. N+1
   extern __shared__ double2 sh[];
@@ -260,8 +264,12 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (nh + 64 * R - 1) / (64 * R);
-  const int m = blockIdx.x / ntile;
-  const int tile = blockIdx.x - m * ntile;
+  // the tiles of one order run on one XCD and share its L2 for the order's
+  // input states and coefficients
+  const int item = xcd_item(blockIdx.x, ntile);
+  const int m = item / ntile;
+  const int tile = item - m * ntile;
+  if (m > N) return;  // uniform across the workgroup
   const int b = blockIdx.y;
   const int K = N + 1 - m;  // degrees m .. N
   extern __shared__ double2 sh[];
@@ -456,13 +464,16 @@ hipError_t launch_synthesis_otf4(const GroupView& g, const SynthInput& in, int m
   dim3 block(kSynthThreads);
   const size_t lds = synthesis_lds_bytes(g.N, 4);
   if (g.nh >= 384 && g.nh % 192 == 0) {
-    dim3 grid3((g.N + 1) * (g.nh / 192), g.nb);
+    const int nt = g.nh / 192;
+    dim3 grid3(xcd_grid((g.N + 1) * nt, nt), g.nb);
     hipLaunchKernelGGL((k_synthesis<TT, 4, 3>), grid3, block, lds, s, g, in, mode);
   } else if (g.nh >= 256) {
-    dim3 grid2((g.N + 1) * ((g.nh + 127) / 128), g.nb);
+    const int nt = (g.nh + 127) / 128;
+    dim3 grid2(xcd_grid((g.N + 1) * nt, nt), g.nb);
     hipLaunchKernelGGL((k_synthesis<TT, 4, 2>), grid2, block, lds, s, g, in, mode);
   } else {
-    dim3 grid((g.N + 1) * ((g.nh + 63) / 64), g.nb);
+    const int nt = (g.nh + 63) / 64;
+    dim3 grid(xcd_grid((g.N + 1) * nt, nt), g.nb);
     hipLaunchKernelGGL((k_synthesis<TT, 4>), grid, block, lds, s, g, in, mode);
   }
   return hipGetLastError();
@@ -471,7 +482,7 @@ hipError_t launch_synthesis_otf4(const GroupView& g, const SynthInput& in, int m
 hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, hipStream_t s) {
   dim3 block(kSynthThreads);
   const int ntile = (g.nh + 63) / 64;
-  dim3 grid((g.N + 1) * ntile, g.nb);
+  dim3 grid(xcd_grid((g.N + 1) * ntile, ntile), g.nb);
   if (mode == SYNTH_ADJ)
     hipLaunchKernelGGL((k_synthesis<double, 5>), grid, block,
                        synthesis_lds_bytes(g.N, 5), s, g, in, mode);
