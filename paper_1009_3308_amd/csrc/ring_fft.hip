@@ -264,6 +264,44 @@ __device__ __forceinline__ void stages_ct(double2* x0, const double2* tw) {
   }
 }
 
+// Forward transform of one LDS array for a compile-time plan whose last stage
+// is radix 3 at stride M/3: every stage before it as in stages_ct, then the
+// last stage computes only its butterflies' first outputs, X_m for m < M/3
+// (they hold every m <= N since 3N + 2 <= M), and stores c X_m for m <= N
+// straight to out[m], without the LDS write-back and its barriers.
+template <int M, int S, int NS, int NT>
+__device__ __forceinline__ void fft_ct_forward_store(double2* x0, const double2* tw, double c,
+                                                     double2* __restrict__ out, int N) {
+  constexpr int n = CtPlan<M>::n;
+  if constexpr (S < n - 1) {
+    constexpr int R = CtPlan<M>::r[S];
+    stage_ct<R, NS, M, 1, NT, -1>(x0, tw);
+    fft_ct_forward_store<M, S + 1, NS * R, NT>(x0, tw, c, out, N);
+  } else {
+    static_assert(CtPlan<M>::r[n - 1] == 3 && NS * 3 == M, "last stage: radix 3 at stride M/3");
+    constexpr int MAXB = (NS + NT - 1) / NT, step = 1, half = M / 2;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int j = threadIdx.x + b * NT;  // butterfly j = k (q = 0 at stride NS = M/3)
+      if (j <= N) {
+        double2 v0 = x0[pad(j)], v1 = x0[pad(j + NS)], v2 = x0[pad(j + 2 * NS)];
+        if (j != 0) {
+          const int e1 = j * step, e2 = 2 * j * step;  // < M
+          double2 w1 = tw[e1 < half ? e1 : e1 - half];
+          if (e1 >= half) w1 = make_double2(-w1.x, -w1.y);
+          double2 w2 = tw[e2 < half ? e2 : e2 - half];
+          if (e2 >= half) w2 = make_double2(-w2.x, -w2.y);
+          v1 = cmul(v1, w1);
+          v2 = cmul(v2, w2);
+        }
+        // first output of the radix-3 butterfly: v0 + (v1 + v2)
+        const double2 t = cadd(v1, v2);
+        out[j] = make_double2(c * (v0.x + t.x), c * (v0.y + t.y));
+      }
+    }
+  }
+}
+
 // Transform of one or two LDS arrays (x1 must be x0 + padded_len(M) when
 // NA = 2): the compile-time plan when CM > 0, else the runtime plan.
 template <int NA, int MAXM, int NT, int CM>
@@ -389,32 +427,29 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
                       N, M, nlat);
   __syncthreads();
   fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
+  // grid product, in place: each index j is read and rewritten by one thread
   const double inv_sin2 = 1.0 / sin2;
-  double q[PTS];
 #pragma unroll
   for (int c = 0; c < PTS; ++c) {
     const int j = threadIdx.x + c * NT;
-    q[c] = 0.0;
     if (j < M) {
       const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
-      q[c] = (z02.x * z02.y - z13.x * z13.y) * inv_sin2;
+      A0[pad(j)] = make_double2((z02.x * z02.y - z13.x * z13.y) * inv_sin2, 0.0);
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int c = 0; c < PTS; ++c) {
-    const int j = threadIdx.x + c * NT;
-    if (j < M) A0[pad(j)] = make_double2(q[c], 0.0);
-  }
-  __syncthreads();
-  fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
   // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
   // own mirror and is folded twice by the analysis
   const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
   double2* Wl = g.W + ((int64_t)b * nlat + lat) * (N + 1);
-  for (int m = threadIdx.x; m <= N; m += blockDim.x) {
-    const double2 X = A0[pad(m)];
-    Wl[m] = make_double2(c * X.x, c * X.y);
+  if constexpr (CM > 0) {
+    fft_ct_forward_store<CM, 0, 1, NT>(A0, tw, c, Wl, N);
+  } else {
+    fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
+    for (int m = threadIdx.x; m <= N; m += blockDim.x) {
+      const double2 X = A0[pad(m)];
+      Wl[m] = make_double2(c * X.x, c * X.y);
+    }
   }
 }
 
