@@ -74,7 +74,7 @@ struct GroupView {
   const double* w;          // [nh]
   const double* T1;         // FP64 synthesis table (layouts above)
   const double* T2;         // FP64 analysis table
-  const float* T1f;         // FP32 copies (precision modes), may be null
+  const float* T1f;         // FP32 copies (split-bf16x3 mode only), else null
   const float* T2f;
   const int64_t* t2off;     // [N+2] start of order m in T2 (element units)
   const double2* rec_a;     // [(N+2)(N+3)/2] (a(l,m), a(l,m) / a(l-1,m)), slot rec_slot(N, l, m)
