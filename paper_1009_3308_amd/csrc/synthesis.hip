@@ -282,14 +282,21 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   // the wave index is uniform across the wave, so the degree bounds are scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pbase = tile * 64 * R + lane;  // latitude of slot r: pbase + 64 r
-  const int chunk = ((K + 2 * kSynthWaves - 1) / (2 * kSynthWaves)) * 2;
-  const int k0 = wave * chunk;  // even
-  const int k1 = min(K, k0 + chunk);
+  // Degree ranges of whole batches: wave 0 takes degree 0 and the degrees
+  // 1 .. chunk, wave w > 0 the degrees 1 + w chunk .. (w + 1) chunk, chunk a
+  // multiple of kB, so no batch straddles two waves; past K the batch reads the
+  // zero padding (its recurrence coefficients and coefficients are zero, so
+  // those degrees add nothing) and the loop needs no per-degree guard.
+  const int chunk = kB * ((K + kSynthWaves * kB - 1) / (kSynthWaves * kB));
+  const int k0 = (wave == 0) ? 0 : 1 + wave * chunk;  // first degree of the wave
+  const int kbs = (wave == 0) ? 1 : k0;                // first degree of its batches (odd)
+  const int k1 = min(K, 1 + (wave + 1) * chunk);
   // The prologue's latencies overlap: the seed rows, the input states and the
   // order's recurrence coefficients (computed once per group, rec_slot) are
   // requested together, and psi and zeta_a are formed from the states directly,
   // so one barrier precedes the loop.
-  // seeds: Pbar at k0 (table row k0) and k0 - 1 (row k0 - 1, zero below m)
+  // seeds: wave 0 Pbar at degree 0 (table row 0); wave w > 0 Pbar at k0 - 1 and
+  // k0 - 2 (rows k0 - 1 and k0 - 2), the batches continuing from them
   double P1[R], P2[R], x[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) P1[r] = P2[r] = x[r] = 0.0;
@@ -299,8 +306,12 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
     for (int r = 0; r < R; ++r) {
       const int p = pbase + 64 * r;
       if (p < nh) {
-        P1[r] = t[(int64_t)k0 * nh + p];
-        if (k0 >= 1) P2[r] = t[(int64_t)(k0 - 1) * nh + p];
+        if (wave == 0) {
+          P1[r] = t[p];
+        } else {
+          P1[r] = t[(int64_t)(k0 - 1) * nh + p];
+          P2[r] = t[(int64_t)(k0 - 2) * nh + p];
+        }
         x[r] = g.mu[p];
       }
     }
@@ -350,9 +361,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
 #pragma unroll
   for (int r = 0; r < R; ++r) XP1[r] = x[r] * P1[r];
   if (k0 < k1) {
-    {
-      // degree k0 (even): Pbar terms to the even part, D terms to the odd part
-      const double2 ps = psi[k0], zz = za[k0], d = dc[k0];
+    if (wave == 0) {
+      // degree 0 (even): Pbar terms to the even part, D terms to the odd part
+      const double2 ps = psi[0], zz = za[0], d = dc[0];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double D = fma(d.y, XP1[r], -d.x * P2[r]);
@@ -366,7 +377,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
         acc[r][13] = fma(P1[r], zz.y, acc[r][13]);
       }
     }
-    if (m == 0 && k0 == 0 && k1 > 1) {
+    if (m == 0 && wave == 0 && k1 > 1) {
       // Coriolis fold: zeta_a[1,0] += coriolis, seen by f2 through D[1]
       // (degree 1 is odd, so D[1] is even); Pbar[1,0] = a(1,0) mu Pbar[0,0]
       const double2 c = rc[1], d = dc[1];
@@ -377,9 +388,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
         acc[r][8] = fma(in.coriolis, D, acc[r][8]);
       }
     }
-    // degrees k0 + 1 .. k1 - 1 in batches of kB (kb odd: degree kb + u is odd
-    // for even u); entries past k1 are padding and are not accumulated
-    for (int kb = k0 + 1; kb < k1; kb += kB) {
+    // degrees kbs .. k1 - 1 in batches of kB (kb odd: degree kb + u is odd for
+    // even u)
+    for (int kb = kbs; kb < k1; kb += kB) {
       double2 c[kB], ps[kB], zz[kB], d[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
@@ -398,19 +409,17 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
           P2[r] = P1[r];
           P1[r] = v;
           XP1[r] = xv;
-          if (kb + u < k1) {
-            const int qp = 2 * ((u + 1) & 1);  // part of the Pbar terms
-            const int qd = 2 - qp;             // part of the D terms
-            const double D = fma(d[u].y, xv, -d[u].x * P2[r]);
-            acc[r][0 + qp] = fma(v, ps[u].x, acc[r][0 + qp]);
-            acc[r][1 + qp] = fma(v, ps[u].y, acc[r][1 + qp]);
-            acc[r][4 + qd] = fma(D, ps[u].x, acc[r][4 + qd]);
-            acc[r][5 + qd] = fma(D, ps[u].y, acc[r][5 + qd]);
-            acc[r][8 + qd] = fma(D, zz[u].x, acc[r][8 + qd]);
-            acc[r][9 + qd] = fma(D, zz[u].y, acc[r][9 + qd]);
-            acc[r][12 + qp] = fma(v, zz[u].x, acc[r][12 + qp]);
-            acc[r][13 + qp] = fma(v, zz[u].y, acc[r][13 + qp]);
-          }
+          const int qp = 2 * ((u + 1) & 1);  // part of the Pbar terms
+          const int qd = 2 - qp;             // part of the D terms
+          const double D = fma(d[u].y, xv, -d[u].x * P2[r]);
+          acc[r][0 + qp] = fma(v, ps[u].x, acc[r][0 + qp]);
+          acc[r][1 + qp] = fma(v, ps[u].y, acc[r][1 + qp]);
+          acc[r][4 + qd] = fma(D, ps[u].x, acc[r][4 + qd]);
+          acc[r][5 + qd] = fma(D, ps[u].y, acc[r][5 + qd]);
+          acc[r][8 + qd] = fma(D, zz[u].x, acc[r][8 + qd]);
+          acc[r][9 + qd] = fma(D, zz[u].y, acc[r][9 + qd]);
+          acc[r][12 + qp] = fma(v, zz[u].x, acc[r][12 + qp]);
+          acc[r][13 + qp] = fma(v, zz[u].y, acc[r][13 + qp]);
         }
       }
     }
