@@ -125,6 +125,29 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def t511_kernels(sph, hist, f, stream, step0, steps):
+    """Per-kernel averages of the T511 FP64 step (instrumented pass as at T255) with
+    their fractions of the FP64 vector rate (synthesis, analysis) and of HBM
+    bandwidth (ring)."""
+    import torch
+    nlat = sph.nlat[0]
+    with torch.cuda.stream(stream):
+        sph.profile(True, repeat=PROFILE_REPEAT)
+        run_steps(sph, hist, f, step0, steps)
+        prof = sph.profile_read()
+        sph.profile(False)
+    abytes = algorithmic_bytes(511, nlat, 2, 3)
+    out = {}
+    for k, (n, ms) in prof.items():
+        if not n:
+            continue
+        avg = ms / n
+        bound, achieved, peak, unit = kernel_roofline(k, 511, nlat, avg, abytes)
+        out[k] = {"avg_us": round(avg * 1e3, 2), "bound": bound, "achieved": round(achieved, 2),
+                  "unit": unit, "frac": round(achieved / peak, 4)}
+    return out
+
+
 def run_steps(sph, hist, f, step0, n):
     sph.step(hist, f, step0, n)
 
@@ -458,6 +481,9 @@ def main():
             s5, h5, f5, st5, wall5, _, fin5 = time_gpu(pkg, torch, 511, 1e-5, steps511, 10,
                                                        precision=prec)
             extra[f"t511_{prec}_steps_per_s"] = round(steps511 / wall5, 2) if fin5 else None
+            if prec == "fp64":
+                extra["t511_fp64_kernels"] = t511_kernels(s5, h5, f5, st5, 10 + steps511,
+                                                          args.profile_steps)
             s5.close()
         for prec in ("fp32", "bf16x3"):
             if extra.get(f"t511_{prec}_steps_per_s") and extra.get("t511_fp64_steps_per_s"):
