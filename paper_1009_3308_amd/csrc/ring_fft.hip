@@ -264,6 +264,54 @@ __device__ __forceinline__ void stages_ct(double2* x0, const double2* tw) {
   }
 }
 
+// Inverse transforms of the two LDS arrays x0 = f0 + i f2 and x1 = f1 + i f3 (x1 =
+// x0 + padded_len(M)) for a compile-time plan whose last stage is radix 3 at
+// stride M/3, fused with the grid product: every stage before the last as in
+// stages_ct; in the last, thread j computes butterfly j of both arrays, whose
+// outputs are the grid values at j, j + M/3 and j + 2M/3 (the positions it
+// read), forms q = (Re x0 Im x0 - Re x1 Im x1) / sin^2 there and writes q in
+// place to x0, so the write-back of the last stage, the separate product pass
+// and two barriers go.
+template <int M, int S, int NS, int NT>
+__device__ __forceinline__ void fft_ct_inverse_product(double2* x0, const double2* tw,
+                                                       double inv_sin2) {
+  constexpr int n = CtPlan<M>::n;
+  if constexpr (S < n - 1) {
+    constexpr int R = CtPlan<M>::r[S];
+    stage_ct<R, NS, M, 2, NT, 1>(x0, tw);
+    fft_ct_inverse_product<M, S + 1, NS * R, NT>(x0, tw, inv_sin2);
+  } else {
+    static_assert(CtPlan<M>::r[n - 1] == 3 && NS * 3 == M, "last stage: radix 3 at stride M/3");
+    constexpr int PL = M + (M >> 4) + 1, MAXB = (NS + NT - 1) / NT, half = M / 2;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int j = threadIdx.x + b * NT;  // butterfly j (q = 0, k = j at stride NS = M/3)
+      if (NS % NT == 0 || j < NS) {
+        double2 v[2][3];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) v[a][r] = x0[a * PL + pad(j + r * NS)];
+#pragma unroll
+          for (int r = 1; r < 3; ++r) {
+            const int e = r * j;  // < M
+            double2 w = tw[e < half ? e : e - half];
+            if (e >= half) w = make_double2(-w.x, -w.y);
+            w.y = -w.y;  // inverse: the table holds exp(-2 pi i e / M)
+            v[a][r] = cmul(v[a][r], w);
+          }
+          butterfly<3>(v[a], 1.0);
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          x0[pad(j + r * NS)] =
+              make_double2((v[0][r].x * v[0][r].y - v[1][r].x * v[1][r].y) * inv_sin2, 0.0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Forward transform of one LDS array for a compile-time plan whose last stage
 // is radix 3 at stride M/3: every stage before it as in stages_ct, then the
 // last stage computes only its butterflies' first outputs, X_m for m < M/3
@@ -422,22 +470,26 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     return;
   }
 
-  // inverse transforms of f0 + i f2 and f1 + i f3
+  // inverse transforms of f0 + i f2 and f1 + i f3, then the grid product
   load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + 2 * fstride, F0 + fstride, F0 + 3 * fstride, lat,
                       N, M, nlat);
   __syncthreads();
-  fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
-  // grid product, in place: each index j is read and rewritten by one thread
   const double inv_sin2 = 1.0 / sin2;
+  if constexpr (CM > 0) {
+    fft_ct_inverse_product<CM, 0, 1, NT>(A0, tw, inv_sin2);
+  } else {
+    fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
+    // grid product, in place: each index j is read and rewritten by one thread
 #pragma unroll
-  for (int c = 0; c < PTS; ++c) {
-    const int j = threadIdx.x + c * NT;
-    if (j < M) {
-      const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
-      A0[pad(j)] = make_double2((z02.x * z02.y - z13.x * z13.y) * inv_sin2, 0.0);
+    for (int c = 0; c < PTS; ++c) {
+      const int j = threadIdx.x + c * NT;
+      if (j < M) {
+        const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
+        A0[pad(j)] = make_double2((z02.x * z02.y - z13.x * z13.y) * inv_sin2, 0.0);
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
   // own mirror and is folded twice by the analysis
   const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
