@@ -51,6 +51,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu_model():
+    """Model name of the host CPU (lscpu / /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def algorithmic_bytes(N, nlat, order, nsrc):
     """HBM bytes each kernel must move per launch (one member). The FP64
     synthesis reads two table rows per wave (four waves per order) and the FP64
@@ -74,19 +86,20 @@ def algorithmic_bytes(N, nlat, order, nsrc):
 
 
 def synthesis_flops(N, nlat):
-    """FP64 flops of one synthesis (one member): per latitude and degree l = m..N+1,
-    eight FMAs of the four complex fields and the recurrence (two multiplies and
-    one FMA): 20 flops."""
-    nh = (nlat + 1) // 2
-    return 20 * nh * sum(N + 2 - m for m in range(N + 1))
+    """Algorithmic FP64 flops of one synthesis (one member), counted as the direct
+    Legendre sums of Section 4.2 define them: for each latitude (both hemispheres)
+    and each (l, m) with 0 <= m <= l <= N+1, a real Legendre value times the four
+    complex field coefficients, 8 flops: 8 nlat (N+2)(N+3)/2. The recurrence that
+    produces the Legendre values in registers is not counted."""
+    return 8 * nlat * (N + 2) * (N + 3) // 2
 
 
 def analysis_flops(N, nlat):
-    """FP64 flops of one analysis (one member): per latitude and degree l = m..N,
-    the recurrence (two multiplies and one FMA) and the complex product-sum (two
-    FMAs): 8 flops."""
-    nh = (nlat + 1) // 2
-    return 8 * nh * sum(N + 1 - m for m in range(N + 1))
+    """Algorithmic FP64 flops of one analysis (one member): a weighted real Legendre
+    value times one complex ring coefficient per latitude and (l, m) with
+    0 <= m <= l <= N, 2 flops per latitude of both hemispheres: 2 nlat (N+1)(N+2)/2.
+    The recurrence is not counted."""
+    return 2 * nlat * (N + 1) * (N + 2) // 2
 
 
 KERNEL_FLOPS = {"synthesis": synthesis_flops, "analysis": analysis_flops}
@@ -152,17 +165,31 @@ def run_steps(sph, hist, f, step0, n):
     sph.step(hist, f, step0, n)
 
 
-def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True, precision="fp64"):
+def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True, precision="fp64", info=None):
+    """Times `steps` NDF2 steps after `warmup` untimed ones. The start-up steps
+    (k <= order) run eagerly; the first call that reaches the fixed-coefficient
+    steps captures the 10-step graph (inside the warm-up when warmup > order), so
+    the timed steps only replay it. The wall time of that capturing warm-up call
+    is reported in `info` (capture_call_ms, capture_call_steps)."""
     import nse_inputs as I
+    order = 2
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sph = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, order=2, graph=graph,
+        sph = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, order=order, graph=graph,
                          stream=stream, precision=precision)
         hist = sph.new_history()
         hist[0] = pkg.to_device(I.initial_state(N))
         f = pkg.to_device(I.forcing(N))
-        run_steps(sph, hist, f, 0, warmup)
+        first = min(warmup, order + 1)
+        run_steps(sph, hist, f, 0, first)
         sph.sync()
+        if warmup > first:
+            t0 = time.perf_counter()
+            run_steps(sph, hist, f, first, warmup - first)
+            sph.sync()
+            if info is not None:
+                info["capture_call_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+                info["capture_call_steps"] = warmup - first
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -178,13 +205,38 @@ def time_gpu(pkg, torch, N, nu, steps, warmup, graph=True, precision="fp64"):
     return sph, hist, f, stream, wall, ev_ms, finite
 
 
+def stored_oracle_trajectory(name):
+    """States of the FP64 oracle's trajectory written by
+    tests/golden/make_trajectories.py, or None if absent or if the seeded inputs
+    no longer match the recorded hash."""
+    import numpy as np
+
+    import nse_inputs as I
+    base = os.path.join(ROOT, "tests", "golden", f"traj_{name}")
+    try:
+        with open(base + ".json") as fh:
+            meta = json.load(fh)
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(I.initial_state(meta["N"])).tobytes())
+        h.update(np.ascontiguousarray(I.forcing(meta["N"])).tobytes())
+        if h.hexdigest() != meta["input_sha256"]:
+            return None
+        with np.load(base + ".npz", allow_pickle=False) as z:
+            return {k: z[k] for k in z.files}
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def precision_errors(pkg, torch, N, nu, steps):
     """Relative l2 error of the grid fields (u_theta, u_phi, zeta) of the reduced-
-    precision runs against the FP64 run after 1 and after `steps` steps."""
+    precision runs after 1 and after `steps` steps, against the FP64 oracle's
+    trajectory (stored; `*_vs_oracle`) and against the FP64 GPU run (`*_vs_fp64`);
+    the FP64 GPU run's own error against the oracle is reported beside them."""
     import numpy as np
 
     import nse_inputs as I
     a0, f = pkg.to_device(I.initial_state(N)), pkg.to_device(I.forcing(N))
+    ref = stored_oracle_trajectory("t511") if N == 511 and steps == 200 else None
     states = {}
     for prec in ("fp64", "fp32", "bf16x3"):
         s = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3, precision=prec)
@@ -196,13 +248,22 @@ def precision_errors(pkg, torch, N, nu, steps):
         states[prec] = (one, h[0].clone())
         s.close()
     s64 = pkg.Sphere([(N, 0, nu)], omega=2 * math.pi, dt=1e-3)
+
+    def field_err(a, b):
+        ga = s64.synthesize(a)[0].cpu().numpy()
+        gb = s64.synthesize(b)[0].cpu().numpy()
+        return max(float(np.linalg.norm(ga[i] - gb[i]) / np.linalg.norm(gb[i])) for i in range(3))
+
     out = {}
-    for prec in ("fp32", "bf16x3"):
-        for idx, tag in ((0, "1step"), (1, f"{steps}steps")):
-            g64 = s64.synthesize(states["fp64"][idx])[0].cpu().numpy()
-            glp = s64.synthesize(states[prec][idx])[0].cpu().numpy()
-            out[f"{prec}_field_err_{tag}"] = max(
-                float(np.linalg.norm(glp[i] - g64[i]) / np.linalg.norm(g64[i])) for i in range(3))
+    for idx, tag in ((0, "1step"), (1, f"{steps}steps")):
+        if ref is not None:
+            r = pkg.to_device(ref["step1" if idx == 0 else f"step{steps}"])
+            out[f"fp64_field_err_{tag}_vs_oracle"] = field_err(states["fp64"][idx], r)
+        for prec in ("fp32", "bf16x3"):
+            if ref is not None:
+                out[f"{prec}_field_err_{tag}_vs_oracle"] = field_err(states[prec][idx], r)
+            out[f"{prec}_field_err_{tag}_vs_fp64"] = field_err(states[prec][idx],
+                                                               states["fp64"][idx])
     s64.close()
     return out
 
@@ -431,8 +492,9 @@ def main():
 
     N, nu = 255, 1e-5
     log(f"bench: T255 FP64 warmup={args.warmup} steps={args.steps}")
+    cap = {}
     sph, hist, f, stream, wall, ev_ms, finite = time_gpu(pkg, torch, N, nu, args.steps,
-                                                         args.warmup)
+                                                         args.warmup, info=cap)
     if not finite:
         raise RuntimeError("state became non-finite during the timed steps")
     ms_per_step = 1e3 * wall / args.steps
@@ -473,7 +535,9 @@ def main():
     sph.close()
 
     extra = {"t255_nonlinear_rel_err_vs_oracle": err, "kernels": kernels,
-             "timed_region_event_ms": round(ev_ms, 3)}
+             "timed_region_event_ms": round(ev_ms, 3),
+             "kernel_sum_us_per_step": round(1e3 * sum(per_kernel.values()), 2),
+             "graph_capture": cap}
     if not args.no_t511:
         steps511 = max(20, args.steps // 5)
         for prec in ("fp64", "fp32", "bf16x3"):
@@ -515,20 +579,31 @@ def main():
     if not args.no_cpu_baseline:
         threads = torch.get_num_threads()
         st = O.Stepper(S, nu, 2 * math.pi, 1e-3, order=2)
-        h = [O.to_tensor(a0)] + [torch.zeros_like(O.to_tensor(a0)) for _ in range(2)]
         fo = O.to_tensor(I.forcing(N))
-        t0 = time.perf_counter()
-        k = 0
-        while True:
-            h = st.step(h, fo, k)
-            k += 1
-            el = time.perf_counter() - t0
-            if k >= 2 and (el > args.cpu_seconds or k >= 200):
-                break
+
+        def oracle_rate(seconds):
+            h = [O.to_tensor(a0)] + [torch.zeros_like(O.to_tensor(a0)) for _ in range(2)]
+            t0 = time.perf_counter()
+            k = 0
+            while True:
+                h = st.step(h, fo, k)
+                k += 1
+                el = time.perf_counter() - t0
+                if k >= 2 and (el > seconds or k >= 200):
+                    return k, el
+
+        k, el = oracle_rate(args.cpu_seconds)
+        torch.set_num_threads(1)
+        k1, el1 = oracle_rate(args.cpu_seconds / 2)
+        torch.set_num_threads(threads)
         cpu = {"value": round(k / el, 4), "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{k} NDF2 steps of the FP64 oracle at N=255 (384x768), "
-                         f"direct DFT and Legendre sums, {el:.1f} s"}
-        log(f"bench: oracle {cpu['value']} steps/s on {threads} threads")
+                         f"direct DFT and Legendre sums, {el:.1f} s on {threads} threads; "
+                         f"{k1} steps in {el1:.1f} s on 1 thread",
+               "value_1_thread": round(k1 / el1, 4),
+               "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
+        log(f"bench: oracle {cpu['value']} steps/s on {threads} threads, "
+            f"{cpu['value_1_thread']} on 1 thread ({cpu['host_cpu']})")
 
     out = {
         "metric": METRIC,

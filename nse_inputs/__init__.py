@@ -22,7 +22,8 @@ Z[l,m] = (l(l+1))^(-1/2) Curl Y[l,m] and u = Curl psi.
 Seeds used by the tests and the benchmark:
     1 initial state, 2 forcing (scale 1e-2), 3 target state, 4 finite-difference
     directions, 5 ensemble viscosities, 6 adjoint cotangents (flat spectrum),
-    7 phases of Example 2's random initial flow, 100+i ensemble member i.
+    7 phases of Example 2's random initial flow, 8 flat spectra (every degree
+    weighted alike), 100+i ensemble member i.
 """
 from __future__ import annotations
 
@@ -108,6 +109,23 @@ def cotangent(N: int, index: int = 0) -> np.ndarray:
     out[ms == 0] = z[ms == 0, 0]
     out[ls == 0] = 0.0
     return out
+
+
+SEED_FLAT = 8
+
+
+def flat_spectrum(N: int, index: int = 0, scale: float = 1.0) -> np.ndarray:
+    """A state with the same law at every degree (no decay): alpha[l,m] = scale * x,
+    x ~ N(0,1) for m = 0 and (z1 + i z2)/sqrt(2) for m > 0, zero at l = 0, drawn
+    in storage order from default_rng(SEED_FLAT * 1000 + index). Every degree and
+    order carries weight, so a full-size comparison sees every coefficient."""
+    rng = np.random.default_rng(SEED_FLAT * 1000 + index)
+    ls, ms = degrees_orders(N)
+    z = rng.standard_normal((len(ls), 2))
+    out = ((z[:, 0] + 1j * z[:, 1]) / np.sqrt(2.0)).astype(np.complex128)
+    out[ms == 0] = z[ms == 0, 0]
+    out[ls == 0] = 0.0
+    return scale * out
 
 
 def grid_noise(seed: int, nlat: int, M: int, fields: int = 2) -> np.ndarray:

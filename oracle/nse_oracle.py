@@ -317,10 +317,6 @@ class Sphere:
         f = 2.0 * omega * self.grid.mu[:, None]
         return clean(self.project(-f * up, f * ut), self.N)
 
-    def kinetic_energy_grid(self, alpha: torch.Tensor) -> torch.Tensor:
-        ut, up = self.velocity(alpha)
-        return 0.5 * self.grid.quad(ut * ut + up * up)
-
 
 # ---------------------------------------------------------------------------
 # Time stepping (ode_disc).

@@ -95,9 +95,13 @@ struct Group {
   }
 };
 
+// A captured chunk of fixed-coefficient steps for one (history, forcing) pair.
 struct GraphEntry {
+  const void* hist = nullptr;
+  const void* forcing = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t used = 0;  // last use, for least-recently-used eviction
 };
 
 }  // namespace
@@ -118,8 +122,9 @@ struct nse_ctx {
   double2* d_iter = nullptr;
   int* d_flag = nullptr;
   std::string err;
-  // captured step chunks keyed by (hist, forcing, chunk length)
-  std::map<std::tuple<const void*, const void*, int>, GraphEntry> graphs;
+  // captured step chunks, at most kGraphCache (history, forcing) pairs
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   // per-kernel timing: every launch is issued `profile_repeat` times between
   // one pair of events (0 = timing off)
   bool profiling = false;
@@ -166,6 +171,9 @@ struct nse_ctx {
 namespace {
 
 constexpr int kGraphChunk = 10;
+// captured step graphs kept per context (each new history or forcing address
+// captures its own; the least recently used is dropped beyond this)
+constexpr size_t kGraphCache = 4;
 constexpr double kPi = 3.14159265358979323846;
 
 nse_status fail(nse_ctx* c, nse_status s, const char* fmt, ...) {
@@ -250,11 +258,17 @@ void free_group(Group& g) {
   (void)hipFree(g.d_nu);
 }
 
+void destroy_graph(GraphEntry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
 void drop_graphs(nse_ctx* c) {
-  for (auto& kv : c->graphs) {
-    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-  }
+  // a graph launched earlier may still run on the stream
+  if (!c->graphs.empty() && c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& g : c->graphs) destroy_graph(g);
   c->graphs.clear();
 }
 
@@ -435,15 +449,15 @@ nse_status time_launches(nse_ctx* c, int reps, F&& launch, float* ms) {
 // Picks the fastest member blocks of every FP64 group with >= 2 members by
 // timing its synthesis and analysis (nonlinear mode) on a zero state.
 nse_status autotune_blocks(nse_ctx* c) {
-  double2* scratch = nullptr;
-  NSE_HIP(c, dalloc(&scratch, (size_t)c->state_count));
-  NSE_HIP(c, hipMemsetAsync(scratch, 0, sizeof(double2) * c->state_count, c->stream));
+  double2* zero_state = nullptr;
+  NSE_HIP(c, dalloc(&zero_state, (size_t)c->state_count));
+  NSE_HIP(c, hipMemsetAsync(zero_state, 0, sizeof(double2) * c->state_count, c->stream));
   nse_status st = NSE_OK;
   for (auto& g : c->groups) {
     if (g.precision != NSE_PREC_FP64 || g.members.size() < 2 || st != NSE_OK) continue;
     SynthInput in{};
     in.nsrc = 1;
-    in.src[0] = scratch;
+    in.src[0] = zero_state;
     in.coef[0] = 1.0;
     AnalOutput out{};
     out.mode = ANAL_NONLINEAR;
@@ -478,7 +492,7 @@ nse_status autotune_blocks(nse_ctx* c) {
     }
   }
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(scratch);
+  (void)hipFree(zero_state);
   return st;
 }
 
@@ -1196,6 +1210,55 @@ nse_status nse_nonlinear(nse_ctx* ctx, const double* alpha, double* n_out) {
   return enqueue_chain(ctx, in, out);
 }
 
+namespace {
+
+// The executable graph of kGraphChunk fixed-coefficient steps (global index
+// k > order) on (h, f), captured on first use; the least recently used entry is
+// dropped once kGraphCache pairs are held.
+static nse_status step_graph(nse_ctx* ctx, double2* h, const double2* f, int64_t k,
+                             hipGraphExec_t* out) {
+  for (auto& g : ctx->graphs) {
+    if (g.hist == (const void*)h && g.forcing == (const void*)f) {
+      g.used = ++ctx->graph_clock;
+      *out = g.exec;
+      return NSE_OK;
+    }
+  }
+  if (ctx->graphs.size() >= kGraphCache) {
+    auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+    // its last launch may still run on the stream
+    NSE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    destroy_graph(*lru);
+    ctx->graphs.erase(lru);
+  }
+  GraphEntry ge;
+  ge.hist = h;
+  ge.forcing = f;
+  NSE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  nse_status s = NSE_OK;
+  for (int i = 0; i < kGraphChunk && s == NSE_OK; ++i) s = enqueue_step(ctx, h, f, k + i);
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
+  if (s != NSE_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+  ge.graph = gr;
+  e = hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    return hip_fail(ctx, e, "hipGraphInstantiate");
+  }
+  ge.used = ++ctx->graph_clock;
+  ctx->graphs.push_back(ge);
+  *out = ge.exec;
+  return NSE_OK;
+}
+
+}  // namespace
+
 nse_status nse_step(nse_ctx* ctx, double* hist, const double* forcing, int64_t step0,
                     int32_t nsteps) {
   if (!ctx) return NSE_ERR_ARG;
@@ -1214,33 +1277,15 @@ nse_status nse_step(nse_ctx* ctx, double* hist, const double* forcing, int64_t s
   }
   const bool graph =
       (ctx->params.flags & NSE_FLAG_GRAPH) && ctx->stream != nullptr && !ctx->profiling;
-  if (graph) {
-    while (end - k >= kGraphChunk) {
-      auto key = std::make_tuple((const void*)hist, (const void*)forcing, kGraphChunk);
-      auto it = ctx->graphs.find(key);
-      if (it == ctx->graphs.end()) {
-        GraphEntry ge;
-        NSE_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-        nse_status s = NSE_OK;
-        for (int i = 0; i < kGraphChunk && s == NSE_OK; ++i) s = enqueue_step(ctx, h, f, k + i);
-        hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
-        if (s != NSE_OK) {
-          if (gr) (void)hipGraphDestroy(gr);
-          return s;
-        }
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
-        ge.graph = gr;
-        e = hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-          (void)hipGraphDestroy(gr);
-          return hip_fail(ctx, e, "hipGraphInstantiate");
-        }
-        it = ctx->graphs.emplace(key, ge).first;
-      }
-      NSE_HIP(ctx, hipGraphLaunch(it->second.exec, ctx->stream));
-      k += kGraphChunk;
-    }
+  if (graph && k < end) {
+    // the first call that reaches the fixed-coefficient steps captures the chunk
+    // graph even when fewer than a chunk of steps remain, so that the capture
+    // cost falls on that call and not on the later calls that replay it
+    hipGraphExec_t exec = nullptr;
+    nse_status s = step_graph(ctx, h, f, k, &exec);
+    if (s != NSE_OK) return s;
+    for (; end - k >= kGraphChunk; k += kGraphChunk)
+      NSE_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
   }
   for (; k < end; ++k) {
     nse_status s = enqueue_step(ctx, h, f, k);

@@ -5,10 +5,16 @@
 // fields a, b with Fourier coefficients G^a_m, G^b_m, m = 0..N, the length-M
 // sequence
 //   x_m = G^a_m + i G^b_m,  x_{M-m} = conj(G^a_m) + i conj(G^b_m)
-// has the inverse DFT g^a_j + i g^b_j. Pairing (f0, f2) and (f1, f3) makes each
-// product of the advection term the real part times the imaginary part of one
-// transform:
-//   q = (f0 f2 - f1 f3) / sin^2(theta) = u . Grad(zeta + 2 Omega cos theta).
+// has the inverse DFT g^a_j + i g^b_j. The pairs are (f0, f1), the two
+// components of the stream-function gradient, and (f2, f3), the two of the
+// absolute-vorticity gradient, so that the advection term is the real part of
+// one product:
+//   q = (f0 f2 - f1 f3) / sin^2(theta) = Re[(f0 + i f1)(f2 + i f3)] / sin^2(theta)
+//     = u . Grad(zeta + 2 Omega cos theta).
+// A transform's rounding error is relative to the larger of its two fields;
+// the vorticity gradient is larger than the stream-function gradient by about
+// the degree squared for a spectrum with weight at high degree, so each
+// transform holds two fields of one kind.
 // One forward FFT of q gives its spectrum Q_m; the quadrature factor
 // (2 pi / M) w_p of eq. (quadrule) is applied and Q_m, m = 0..N, is written for
 // the ring (W[lat][m]); the analysis folds the two rings of each latitude
@@ -264,14 +270,13 @@ __device__ __forceinline__ void stages_ct(double2* x0, const double2* tw) {
   }
 }
 
-// Inverse transforms of the two LDS arrays x0 = f0 + i f2 and x1 = f1 + i f3 (x1 =
+// Inverse transforms of the two LDS arrays x0 = f0 + i f1 and x1 = f2 + i f3 (x1 =
 // x0 + padded_len(M)) for a compile-time plan whose last stage is radix 3 at
 // stride M/3, fused with the grid product: every stage before the last as in
 // stages_ct; in the last, thread j computes butterfly j of both arrays, whose
 // outputs are the grid values at j, j + M/3 and j + 2M/3 (the positions it
-// read), forms q = (Re x0 Im x0 - Re x1 Im x1) / sin^2 there and writes q in
-// place to x0, so the write-back of the last stage, the separate product pass
-// and two barriers go.
+// read), forms q = Re(x0 x1) / sin^2 there and writes q in place to x0, so the
+// write-back of the last stage, the separate product pass and two barriers go.
 template <int M, int S, int NS, int NT>
 __device__ __forceinline__ void fft_ct_inverse_product(double2* x0, const double2* tw,
                                                        double inv_sin2) {
@@ -305,7 +310,7 @@ __device__ __forceinline__ void fft_ct_inverse_product(double2* x0, const double
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           x0[pad(j + r * NS)] =
-              make_double2((v[0][r].x * v[0][r].y - v[1][r].x * v[1][r].y) * inv_sin2, 0.0);
+              make_double2((v[0][r].x * v[1][r].x - v[0][r].y * v[1][r].y) * inv_sin2, 0.0);
       }
     }
     __syncthreads();
@@ -470,8 +475,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     return;
   }
 
-  // inverse transforms of f0 + i f2 and f1 + i f3, then the grid product
-  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + 2 * fstride, F0 + fstride, F0 + 3 * fstride, lat,
+  // inverse transforms of f0 + i f1 and f2 + i f3, then the grid product
+  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + fstride, F0 + 2 * fstride, F0 + 3 * fstride, lat,
                       N, M, nlat);
   __syncthreads();
   const double inv_sin2 = 1.0 / sin2;
@@ -484,8 +489,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
     for (int c = 0; c < PTS; ++c) {
       const int j = threadIdx.x + c * NT;
       if (j < M) {
-        const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
-        A0[pad(j)] = make_double2((z02.x * z02.y - z13.x * z13.y) * inv_sin2, 0.0);
+        const double2 z01 = A0[pad(j)], z23 = A1[pad(j)];
+        A0[pad(j)] = make_double2((z01.x * z23.x - z01.y * z23.y) * inv_sin2, 0.0);
       }
     }
     __syncthreads();
@@ -541,8 +546,9 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
     const int m = threadIdx.x + i * NT;
     qbar[i] = (m <= N) ? F5[4 * fstride + (int64_t)m * nlat + lat] : make_double2(0.0, 0.0);
   }
-  // forward grid fields of this ring
-  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F5, F5 + 2 * fstride, F5 + fstride, F5 + 3 * fstride, lat,
+  // forward grid fields of this ring: f0 + i f1 and f2 + i f3 (pairs of one
+  // kind, as in k_ring)
+  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F5, F5 + fstride, F5 + 2 * fstride, F5 + 3 * fstride, lat,
                       N, M, nlat);
   __syncthreads();
   fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
@@ -552,11 +558,11 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
     const int j = threadIdx.x + c * NT;
     g0[c] = g1[c] = g2[c] = g3[c] = 0.0;
     if (j < M) {
-      const double2 z02 = A0[pad(j)], z13 = A1[pad(j)];
-      g0[c] = z02.x;
-      g2[c] = z02.y;
-      g1[c] = z13.x;
-      g3[c] = z13.y;
+      const double2 z01 = A0[pad(j)], z23 = A1[pad(j)];
+      g0[c] = z01.x;
+      g1[c] = z01.y;
+      g2[c] = z23.x;
+      g3[c] = z23.y;
     }
   }
   __syncthreads();
@@ -587,8 +593,9 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   for (int c = 0; c < PTS; ++c) {
     const int j = threadIdx.x + c * NT;
     if (j < M) {
-      A0[pad(j)] = make_double2(qb[c] * g2[c], qb[c] * g0[c]);     // gbar0 + i gbar2
-      A1[pad(j)] = make_double2(-qb[c] * g3[c], -qb[c] * g1[c]);   // gbar1 + i gbar3
+      // gbar0 + i gbar1 (both of the vorticity-gradient size) and gbar2 + i gbar3
+      A0[pad(j)] = make_double2(qb[c] * g2[c], -qb[c] * g3[c]);
+      A1[pad(j)] = make_double2(qb[c] * g0[c], -qb[c] * g1[c]);
     }
   }
   __syncthreads();
@@ -605,8 +612,8 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
       const double2 zc = X[pad((M - m) % M)];
       const double2 ga = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
       const double2 gb = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
-      Fb[(int64_t)(arr ? 1 : 0) * fstride + m] = ga;
-      Fb[(int64_t)(arr ? 3 : 2) * fstride + m] = gb;
+      Fb[(int64_t)(arr ? 2 : 0) * fstride + m] = ga;
+      Fb[(int64_t)(arr ? 3 : 1) * fstride + m] = gb;
     }
   }
 }

@@ -191,9 +191,13 @@ def test_trajectory_gradient_vs_oracle_autograd(every):
     s.close()
 
 
-def test_trajectory_gradient_finite_differences_t255():
+# "decaying": directions of the workload's spectral shape; "flat": the same law at
+# every degree (scaled to a comparable norm), so the gradient's high degrees and
+# orders are checked too
+@pytest.mark.parametrize("shape", ["decaying", "flat"])
+def test_trajectory_gradient_finite_differences_t255(shape):
     N, nu, dt, steps, ndir = 255, 1e-5, 1e-3, 200, 32
-    _say(f"case: T255 gradient vs central differences, {steps} steps, {ndir} directions")
+    _say(f"case: T255 gradient vs central differences, {steps} steps, {ndir} {shape} directions")
     s = pkg.Sphere([(N, 0, nu)], omega=OMEGA, dt=dt, graph=True)
     f, tg = pkg.to_device(I.forcing(N)), pkg.to_device(I.target_state(N))
     a0 = pkg.to_device(I.initial_state(N))
@@ -208,7 +212,10 @@ def test_trajectory_gradient_finite_differences_t255():
     L = _gpu_loss(trajectory(s, a, f, steps, checkpoint_every=20), tg, N)
     (g,) = torch.autograd.grad(L, a)
     assert abs(float(L.detach()) - loss(a0)) <= 1e-14 * abs(float(L.detach()))
-    dirs = I.directions(N, ndir)
+    if shape == "decaying":
+        dirs = I.directions(N, ndir)
+    else:
+        dirs = np.stack([I.flat_spectrum(N, 100 + i, scale=1e-2) for i in range(ndir)])
     t = 1e-4
     fd, gd = [], []
     for i in range(ndir):

@@ -1,8 +1,8 @@
 """Diagnostics of the experiments on the GPU against the oracle: the energy spectrum
 E(L) (eq. (energy)), the stream function Psi_N (eq. (eq:vort_app)) and the
 approximate inertial manifold (eq. (eq:p-p)), through the C ABI. Bar 1e-12
-relative (FP64 path); for the manifold, relative to the size of f - B(u1, u1)
-after applying (nu A + C) to the difference."""
+relative (FP64 path); for the manifold every coefficient against the largest
+coefficient of the band (N1, N'], on inputs whose product fills that band."""
 import math
 import os
 
@@ -74,9 +74,9 @@ def test_stream_function(N, prec):
 def test_inertial_manifold(N1, Np, n_src, nu, omega):
     _say(f"case inertial manifold N1={N1} N'={Np} n_src={n_src}")
     if n_src == 100:
-        # an evolved flow fills every degree (the initial one stops at 20, whose
-        # product stays below degree 41 and leaves the band (75, 150] empty)
-        a = I.spectrum(I.SEED_INITIAL, n_src)
+        # a flat spectrum gives u1 = P_N1 u weight at every degree <= N1, so that
+        # B(u1, u1) fills the whole band (N1, 2 N1] with values of one size
+        a = I.flat_spectrum(n_src, 3)
         f = np.zeros(I.coeff_count(Np), dtype=np.complex128)
         f[I.index(Np, 3, 0)] = 1.0
     else:
@@ -89,17 +89,17 @@ def test_inertial_manifold(N1, Np, n_src, nu, omega):
     S = O.Sphere(Np)
     ref = O.inertial_manifold(S, O.to_tensor(a), n_src, N1, O.to_tensor(f), nu, omega)
     ref0 = O.inertial_manifold(S, O.to_tensor(a), n_src, N1, None, nu, omega)
-    # residual bar: (nu A + C)(phi - phi_ref) against the size of f - B(u1, u1) over all
-    # degrees (the band values can be many orders below it for a decaying spectrum)
-    b = S.nonlinear(O.embed(O.to_tensor(a), n_src, Np, N1), 0.0)
-    lam = S.lam.clone()
-    lam[0] = 1.0
-    diag = nu * lam - 2j * omega * O.orders(Np) / lam
-    for got, r, ff in ((phi, ref, O.to_tensor(f)), (phi0, ref0, None)):
-        scale = float(((ff if ff is not None else 0) - b).abs().max())
-        assert float(r.abs().max()) > 0
-        assert float(((got - r) * diag).abs().max()) <= 1e-12 * scale
     deg = torch.as_tensor(I.degrees_orders(Np)[0])
+    band = (deg > N1) & (deg <= Np)
+    for got, r in ((phi, ref), (phi0, ref0)):
+        # every band degree that B(u1, u1) can reach (N1 < L <= 2 N1 - 2; the two top
+        # degrees of the product of two degree-N1 fields vanish) carries content, so
+        # this is no comparison of rounding with rounding
+        rms = [float(r[deg == L].abs().pow(2).mean().sqrt()) for L in range(N1 + 1, 2 * N1 - 1)]
+        assert min(rms) > 1e-6 * max(rms)
+        e = float((got - r).abs().max()) / float(r[band].abs().max())
+        _say(f"  max coefficient err / max {e:.3e}; band degree RMS spread {min(rms) / max(rms):.2e}")
+        assert e <= 1e-12
     assert float(phi[deg <= N1].abs().max()) == 0.0
 
 

@@ -115,6 +115,36 @@ def test_discrete_orthonormality_full_table():
         assert torch.allclose(gram, torch.eye(P.shape[0], dtype=torch.float64), atol=1e-13)
 
 
+# the full-size grids: every degree l <= N+1 of the selected orders, up to the
+# sectoral end m = N+1 and orders above 400 at N = 511, where the values near the
+# poles underflow (sin^m) and the recurrence runs over 500 degrees
+@pytest.mark.parametrize("N,orders", [(255, (0, 1, 37, 128, 200, 255, 256)),
+                                      (511, (0, 1, 37, 255, 400, 450, 500, 511, 512))])
+def test_discrete_orthonormality_full_degree(N, orders):
+    g = O.Grid(O.min_nlat(N))
+    for m in orders:
+        P = O.legendre_order(m, N + 1, g.mu, g.sin)
+        gram = 2.0 * math.pi * (P * g.w) @ P.T
+        err = float((gram - torch.eye(P.shape[0], dtype=torch.float64)).abs().max())
+        assert err < 1e-13, (m, err)
+
+
+@pytest.mark.parametrize("N", [255, 511])
+def test_legendre_high_degree_vs_scipy(N):
+    """Pbar[l,m] at the Gauss nodes against scipy's normalised associated Legendre
+    function for degrees up to N+1 (the library runs its own recurrence; after
+    ~500 degrees both carry ~l ulps of rounding on values up to sqrt((2l+1)/(4 pi)))."""
+    g = O.Grid(O.min_nlat(N))
+    th = np.arccos(g.mu.numpy())
+    for m in (0, 1, 37, N // 2, 400 if N > 400 else N - 1, N, N + 1):
+        P = O.legendre_order(m, N + 1, g.mu, g.sin).numpy()
+        for l in sorted({m, min(m + 1, N + 1), (m + N + 1) // 2, N, N + 1}):
+            if l < m:
+                continue
+            v = sp.sph_legendre_p(l, m, th)
+            assert np.abs(P[l - m] - v).max() < 1e-11, (l, m)
+
+
 # --------------------------------------------------------------------------- P3
 @pytest.mark.parametrize("N", [7, 31])
 def test_scalar_and_vector_round_trip(N):
