@@ -169,6 +169,23 @@ nse_status nse_step(nse_ctx* ctx, double* hist, const double* forcing,
 nse_status nse_nonlinear_adjoint(nse_ctx* ctx, const double* alpha,
                                  const double* n_bar, double* alpha_bar);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as nse_nonlinear_adjoint (the same kernels), with the adjoint's
+ * Fourier intermediates (5 + 4 field slabs of nlat x (N+1) complex values and
+ * (N+1)(N+2)x4 panel cotangents per member, each group's pieces 256-byte
+ * aligned) placed in a static device array of 32 MiB that the library holds on
+ * every device it runs on until the process ends, instead of buffers the
+ * context allocates on first use. It calls no allocator. One member up to
+ * N = 255 on its default grid fits (18.4 MB); a context that needs more returns
+ * NSE_ERR_ARG and enqueues nothing. The array is shared by every call on one
+ * device and keeps the last call's contents (every entry a call reads it first
+ * writes, so nothing needs clearing): calls that overlap on one device (other
+ * streams, other contexts, other host threads) race. Arguments, layout and
+ * errors as nse_nonlinear_adjoint. */
+nse_status nse_nonlinear_adjoint_noalloc(nse_ctx* ctx, const double* alpha,
+                                         const double* n_bar, double* alpha_bar);
+
 /* Adjoint of one nse_step call with nsteps = 1 at global step index `step`:
  * hist is the history BEFORE that step ([order+1][state], device), hist_bar
  * holds dL/d(history after the step) on input and dL/d(history before the

@@ -40,6 +40,7 @@ EXPORTS = (
     "nse_analyze_velocity", "nse_get_member_blocks", "nse_set_member_blocks",
     "nse_adaptive_begin", "nse_adaptive_advance", "nse_adaptive_log",
     "nse_energy_spectrum", "nse_synthesize_psi", "nse_inertial_manifold",
+    "nse_nonlinear_adjoint_noalloc",
 )
 
 ATTEMPT_ACCEPTED, ATTEMPT_ERROR_FAIL, ATTEMPT_NEWTON_FAIL = 0, 1, 2
@@ -113,6 +114,7 @@ def lib():
         "nse_nonlinear": (st, [vp, dp, dp]),
         "nse_step": (st, [vp, dp, dp, i64, i32]),
         "nse_nonlinear_adjoint": (st, [vp, dp, dp, dp]),
+        "nse_nonlinear_adjoint_noalloc": (st, [vp, dp, dp, dp]),
         "nse_step_adjoint": (st, [vp, dp, dp, i64, dp]),
         "nse_synthesize": (st, [vp, dp, dp]),
         "nse_analyze_velocity": (st, [vp, dp, dp]),
@@ -261,6 +263,17 @@ class Sphere:
         if out is None:
             out = self.new_state()
         _check(lib().nse_nonlinear_adjoint(
+            self._handle(), _ptr(alpha, torch.complex128, self.state_count, "alpha"),
+            _ptr(n_bar, torch.complex128, self.state_count, "n_bar"),
+            _ptr(out, torch.complex128, self.state_count, "alpha_bar")), self._h)
+        return out
+
+    def nonlinear_adjoint_noalloc(self, alpha, n_bar, out):
+        """nse_nonlinear_adjoint_noalloc: the same product with the library's static
+        scratch in place of allocated intermediates; `out` must be given (nothing is
+        allocated here either)."""
+        import torch
+        _check(lib().nse_nonlinear_adjoint_noalloc(
             self._handle(), _ptr(alpha, torch.complex128, self.state_count, "alpha"),
             _ptr(n_bar, torch.complex128, self.state_count, "n_bar"),
             _ptr(out, torch.complex128, self.state_count, "alpha_bar")), self._h)

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -20,6 +21,13 @@
 #include "nse_internal.h"
 
 using namespace nse;
+
+// Scratch of nse_nonlinear_adjoint_noalloc (the adjoint's Fourier intermediates
+// for callers that cannot allocate): one copy per device, held until the process
+// ends. Host code never passes this name to a kernel; it uses the device address
+// that hipGetSymbolAddress returns for the current device (bind_noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double2 scratch[kNoAllocScratchBytes / sizeof(double2)];
 
 namespace {
 
@@ -166,6 +174,8 @@ struct nse_ctx {
   unsigned long long* h_pub = nullptr;     // host-mapped: norms of every sweep + sequence word
   unsigned long long* d_pub = nullptr;     // its device address
   unsigned long long pub_seq = 0;
+  // device address of this device's static scratch (nse_nonlinear_adjoint_noalloc)
+  double2* noalloc_scratch = nullptr;
 };
 
 namespace {
@@ -623,11 +633,26 @@ nse_status ensure_adjoint_buffers(nse_ctx* c) {
 // alpha_bar = J^T n_bar at the synthesis input `in` (always FP64 tables):
 // recompute the forward spectra with the analysis cotangent as a fifth field,
 // then the transposed ring, synthesis and prologue.
+// `scratch_base` (optional): device memory of noalloc_bytes(c) bytes that holds
+// the groups' Fa, Fbar and Pbar instead of the context's own buffers.
 nse_status enqueue_nonlinear_adjoint(nse_ctx* c, SynthInput in, const double2* n_bar,
-                                     double2* alpha_bar) {
+                                     double2* alpha_bar, double2* scratch_base = nullptr) {
   in.adj = n_bar;
+  char* sp = (char*)scratch_base;
+  auto carve = [&](size_t bytes) {
+    double2* p = (double2*)sp;
+    sp += (bytes + 255) & ~size_t(255);
+    return p;
+  };
   for (auto& g : c->groups) {
-    const GroupView v = g.view();
+    GroupView v = g.view();
+    if (scratch_base) {
+      const size_t nb = g.members.size();
+      const size_t fs = (size_t)g.nlat * (g.N + 1);
+      v.Fa = carve(sizeof(double2) * nb * 5 * fs);
+      v.Fbar = carve(sizeof(double2) * nb * 4 * fs);
+      v.Pbar = carve(sizeof(double2) * nb * (size_t)(g.N + 1) * (g.N + 2) * 4);
+    }
     NSE_HIP(c, launch_synthesis(v, in, SYNTH_ADJ, c->stream));
     NSE_HIP(c, launch_ring_adjoint(v, g.plan, c->stream));
     NSE_HIP(c, launch_synthesis_adjoint(v, c->stream));
@@ -994,6 +1019,46 @@ int64_t nse_coeff_count(int32_t N) {
 
 int64_t nse_state_count(const nse_ctx* ctx) { return ctx ? ctx->state_count : -1; }
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double2* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static scratch on the current device, looked up once
+// per device (with that device current) and kept for the process.
+static nse_status bind_noalloc_scratch(nse_ctx* c) {
+  int dev = -1;
+  NSE_HIP(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(c, NSE_ERR_UNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    NSE_HIP(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(c, NSE_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch");
+    g_scratch_ptr[dev] = (double2*)p;
+  }
+  c->noalloc_scratch = g_scratch_ptr[dev];
+  return NSE_OK;
+}
+
+// Bytes of adjoint intermediates (Fa, Fbar, Pbar of every group) carved from the
+// static scratch, each piece 256-byte aligned.
+static size_t noalloc_bytes(const nse_ctx* c) {
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t total = 0;
+  for (const auto& g : c->groups) {
+    const size_t nb = g.members.size();
+    const size_t fs = (size_t)g.nlat * (g.N + 1);
+    total += up(sizeof(double2) * nb * 5 * fs) + up(sizeof(double2) * nb * 4 * fs) +
+             up(sizeof(double2) * nb * (size_t)(g.N + 1) * (g.N + 2) * 4);
+  }
+  return total;
+}
+
+}  // namespace
+
 nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const nse_params* params,
                            void* hip_stream, nse_ctx** out) {
   g_init_error.clear();
@@ -1113,6 +1178,10 @@ nse_status nse_sphere_init(const nse_member* members, int32_t n_members, const n
   if (e == hipSuccess) e = hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return cleanup(hip_fail(c.get(), e, "init"));
+  {
+    nse_status s = bind_noalloc_scratch(c.get());
+    if (s != NSE_OK) return cleanup(s);
+  }
   if (P.flags & NSE_FLAG_AUTOTUNE) {
     nse_status s = autotune_blocks(c.get());
     if (s != NSE_OK) return cleanup(s);
@@ -1308,6 +1377,28 @@ nse_status nse_nonlinear_adjoint(nse_ctx* ctx, const double* alpha, const double
   in.coef[0] = 1.0;
   in.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
   return enqueue_nonlinear_adjoint(ctx, in, (const double2*)n_bar, (double2*)alpha_bar);
+}
+
+nse_status nse_nonlinear_adjoint_noalloc(nse_ctx* ctx, const double* alpha, const double* n_bar,
+                                         double* alpha_bar) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!alpha || !n_bar || !alpha_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  if (alpha_bar == alpha || alpha_bar == n_bar)
+    return fail(ctx, NSE_ERR_ARG, "alpha_bar may not alias alpha or n_bar");
+  const size_t need = noalloc_bytes(ctx);
+  if (need > kNoAllocScratchBytes)
+    return fail(ctx, NSE_ERR_ARG,
+                "the context needs %zu bytes of adjoint scratch; the static scratch holds %zu "
+                "(use nse_nonlinear_adjoint)",
+                need, kNoAllocScratchBytes);
+  if (!ctx->noalloc_scratch) return fail(ctx, NSE_ERR_STATE, "static scratch not bound");
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = (const double2*)alpha;
+  in.coef[0] = 1.0;
+  in.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  return enqueue_nonlinear_adjoint(ctx, in, (const double2*)n_bar, (double2*)alpha_bar,
+                                   ctx->noalloc_scratch);
 }
 
 nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forcing, int64_t step,
