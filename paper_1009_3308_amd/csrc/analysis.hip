@@ -16,8 +16,10 @@
 // after rotating hist[j] <- hist[j-1].
 //
 // Workgroups of four waves per (order m, tile of 64 degrees, member). Orders
-// are taken in XCD-local chunks of four neighbouring m so that the strided
-// reads of W[lat][m] share L2 lines.
+// are taken in XCD-local chunks of four neighbouring m. The ring spectra
+// W[m][lat] of an order are contiguous, so the fold's loads are coalesced; the
+// step update's inputs (forcing, history) of the tile's 64 degrees are
+// requested with them and wait in LDS, so the epilogue issues no load.
 #include "lane_ops.h"
 #include "spectral_ops.h"
 
@@ -53,8 +55,9 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
   const int tile = item - m * ntile;
   if (m > N || tile * 64 > N - m) return;  // uniform across the workgroup
   const int b = blockIdx.y;
-  extern __shared__ double2 wsh[];  // We [nh], Wo [nh], rc [64]
+  extern __shared__ double2 wsh[];  // We [nh], Wo [nh], rc [64], step inputs [64][kDegreeInputs]
   double2* rc = wsh + 2 * nh;
+  double2* pre = rc + 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int kt = tile * 64;  // first degree offset k = l - m of the tile
@@ -83,17 +86,21 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
   // requested before the coefficient pairs are computed, so that their square
   // roots and the LDS writes wait for one memory round trip
   static_assert(kMaxM / 4 <= 2 * kAnalThreads, "two ring pairs per thread");
-  const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
+  const double2* Wb = g.W + ((int64_t)b * (N + 1) + m) * g.nlat;
   double2 qn[2], qs[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int p = threadIdx.x + i * kAnalThreads;
     qn[i] = qs[i] = make_double2(0.0, 0.0);
     if (p < nh) {
-      qn[i] = Wb[(int64_t)p * (N + 1)];
-      qs[i] = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+      qn[i] = Wb[p];
+      qs[i] = Wb[g.nlat - 1 - p];
     }
   }
+  // the step update's inputs of degree kt + t (wave 0), kept until the epilogue
+  double2 din[kDegreeInputs];
+  const bool dthread = threadIdx.x < 64 && kt + (int)threadIdx.x <= N - m;
+  if (dthread) load_degree_inputs(g, out, b, m, kt + threadIdx.x, din);
   // recurrence pairs of the tile's degrees (k >= 2 of the order, from the
   // group's coefficient table; zero past degree N+1, whose values are not used)
   if (threadIdx.x < 64) {
@@ -108,6 +115,10 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       wsh[p] = make_double2(qn[i].x + qs[i].x, qn[i].y + qs[i].y);
       wsh[nh + p] = make_double2(qn[i].x - qs[i].x, qn[i].y - qs[i].y);
     }
+  }
+  if (dthread && out.mode != ANAL_NONLINEAR) {
+#pragma unroll
+    for (int i = 0; i < kDegreeInputs; ++i) pre[threadIdx.x * kDegreeInputs + i] = din[i];
   }
   __syncthreads();
   if (!active) return;
@@ -154,12 +165,15 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
                 ((lane >> 2) & 1);
   const int k = kt + j0 + j;
   if (k > N - m) return;
-  finish_degree(g, out, b, m, k, (double)sr[0], (double)si[0]);
+  finish_degree_from(g, out, b, m, k, (double)sr[0], (double)si[0],
+                     pre + (k - kt) * kDegreeInputs);
 }
 
 }  // namespace
 
-size_t analysis_otf_lds_bytes(int nh) { return sizeof(double2) * (size_t)(2 * nh + 64); }
+size_t analysis_otf_lds_bytes(int nh) {
+  return sizeof(double2) * (size_t)(2 * nh + 64 + 64 * kDegreeInputs);
+}
 
 template <typename TT>
 hipError_t launch_analysis_otf(dim3 grid, dim3 block, size_t lds, hipStream_t s,

@@ -235,10 +235,10 @@ __global__ __launch_bounds__(kLpThreads) void k_analysis_lp(GroupView g, AnalOut
   const int nblk = (nh + 31) / 32;
   extern __shared__ double2 wsh[];  // We [nh], Wo [nh], then the split A operand
   bf16x8* asplit = reinterpret_cast<bf16x8*>(wsh + 2 * nh);  // [nblk][3][16]
-  const double2* Wb = g.W + (int64_t)b * g.nlat * (N + 1) + m;
+  const double2* Wb = g.W + ((int64_t)b * (N + 1) + m) * g.nlat;
   for (int p = threadIdx.x; p < nh; p += blockDim.x) {
-    const double2 qn = Wb[(int64_t)p * (N + 1)];
-    const double2 qs = Wb[(int64_t)(g.nlat - 1 - p) * (N + 1)];
+    const double2 qn = Wb[p];
+    const double2 qs = Wb[g.nlat - 1 - p];
     wsh[p] = make_double2(qn.x + qs.x, qn.y + qs.y);
     wsh[nh + p] = make_double2(qn.x - qs.x, qn.y - qs.y);
   }

@@ -73,9 +73,9 @@ __global__ __launch_bounds__(kMbThreads) void k_analysis_mb(GroupView g, AnalOut
       const int p = pc + pp, b = b0 + bb;
       wn[j] = ws[j] = make_double2(0.0, 0.0);
       if (i < 64 * B && p < nh && b < g.nb) {
-        const double2* Wb = g.W + (int64_t)b * nlat * (N + 1) + m;
-        wn[j] = Wb[(int64_t)p * (N + 1)];
-        ws[j] = Wb[(int64_t)(nlat - 1 - p) * (N + 1)];
+        const double2* Wb = g.W + ((int64_t)b * (N + 1) + m) * nlat;
+        wn[j] = Wb[p];
+        ws[j] = Wb[nlat - 1 - p];
       }
     }
   };

@@ -83,7 +83,8 @@ struct GroupView {
   double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
   double2* Fbar;            // adjoint: [nb][4][nlat][N+1] cotangents of the field spectra
   double2* Pbar;            // adjoint: [nb][N+1][N+2][4] cotangents of the panels
-  double2* W;               // [nb][nlat][N+1] weighted ring spectra (analysis input)
+  double2* W;               // [nb][N+1][nlat] weighted ring spectra (analysis input),
+                            // latitude fastest so the analysis reads them coalesced
   uint64_t* lps;            // split-bf16 synthesis panels, 8-byte groups (precision BF16X3)
   const int64_t* lpsoff;    // [N+2] start of order m in one member's lps (member stride lpsoff[N+1])
   const double2* tw;        // [M] exp(-2 pi i k / M)

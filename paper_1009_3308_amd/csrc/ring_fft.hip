@@ -17,8 +17,8 @@
 // transform holds two fields of one kind.
 // One forward FFT of q gives its spectrum Q_m; the quadrature factor
 // (2 pi / M) w_p of eq. (quadrule) is applied and Q_m, m = 0..N, is written for
-// the ring (W[lat][m]); the analysis folds the two rings of each latitude
-// pair.
+// the ring (W[m][lat], latitude fastest); the analysis folds the two rings of
+// each latitude pair.
 //
 // The FFT is a mixed-radix (8, 4, 2, 5, 3) Stockham transform done in place in
 // LDS: each stage reads R values at stride M/R into registers, applies
@@ -321,15 +321,16 @@ __device__ __forceinline__ void fft_ct_inverse_product(double2* x0, const double
 // is radix 3 at stride M/3: every stage before it as in stages_ct, then the
 // last stage computes only its butterflies' first outputs, X_m for m < M/3
 // (they hold every m <= N since 3N + 2 <= M), and stores c X_m for m <= N
-// straight to out[m], without the LDS write-back and its barriers.
+// straight to out[m * ostride], without the LDS write-back and its barriers.
 template <int M, int S, int NS, int NT>
 __device__ __forceinline__ void fft_ct_forward_store(double2* x0, const double2* tw, double c,
-                                                     double2* __restrict__ out, int N) {
+                                                     double2* __restrict__ out, int64_t ostride,
+                                                     int N) {
   constexpr int n = CtPlan<M>::n;
   if constexpr (S < n - 1) {
     constexpr int R = CtPlan<M>::r[S];
     stage_ct<R, NS, M, 1, NT, -1>(x0, tw);
-    fft_ct_forward_store<M, S + 1, NS * R, NT>(x0, tw, c, out, N);
+    fft_ct_forward_store<M, S + 1, NS * R, NT>(x0, tw, c, out, ostride, N);
   } else {
     static_assert(CtPlan<M>::r[n - 1] == 3 && NS * 3 == M, "last stage: radix 3 at stride M/3");
     constexpr int MAXB = (NS + NT - 1) / NT, step = 1, half = M / 2;
@@ -349,7 +350,7 @@ __device__ __forceinline__ void fft_ct_forward_store(double2* x0, const double2*
         }
         // first output of the radix-3 butterfly: v0 + (v1 + v2)
         const double2 t = cadd(v1, v2);
-        out[j] = make_double2(c * (v0.x + t.x), c * (v0.y + t.y));
+        out[(int64_t)j * ostride] = make_double2(c * (v0.x + t.x), c * (v0.y + t.y));
       }
     }
   }
@@ -498,14 +499,16 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
   // own mirror and is folded twice by the analysis
   const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
-  double2* Wl = g.W + ((int64_t)b * nlat + lat) * (N + 1);
+  // W[b][m][lat]: stride nlat between orders (the eight rings of an XCD chunk
+  // fill whole cache lines of one order)
+  double2* Wl = g.W + (int64_t)b * (N + 1) * nlat + lat;
   if constexpr (CM > 0) {
-    fft_ct_forward_store<CM, 0, 1, NT>(A0, tw, c, Wl, N);
+    fft_ct_forward_store<CM, 0, 1, NT>(A0, tw, c, Wl, nlat, N);
   } else {
     fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
     for (int m = threadIdx.x; m <= N; m += blockDim.x) {
       const double2 X = A0[pad(m)];
-      Wl[m] = make_double2(c * X.x, c * X.y);
+      Wl[(int64_t)m * nlat] = make_double2(c * X.x, c * X.y);
     }
   }
 }

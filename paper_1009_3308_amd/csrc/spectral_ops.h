@@ -114,8 +114,34 @@ __device__ inline void build_panel(double2* pan, const double2* a, int N, int m,
 //   alpha_new = (h (f - n) - sum_{j>=1} c_j hist[j-1]) / (c_0 + h nu lambda_l),
 // written as the next fixed-point iterate or, on the last sweep, to hist[0]
 // after rotating hist[j] <- hist[j-1] (eq. (ode_disc), eq. (stok_eig)).
+// Inputs of the step update of degree l = m + k, in[0] = f[l,m] (zero without
+// forcing) and in[1 + j] = hist[j][l,m] for j < depth; nothing in the nonlinear
+// mode. Kernels can request them early and keep them until finish_degree_from.
+constexpr int kDegreeInputs = kMaxStepCoef;  // forcing + up to kMaxStepCoef - 1 history slots
+__device__ inline void load_degree_inputs(const GroupView& g, const AnalOutput& out, int b, int m,
+                                          int k, double2* in) {
+  if (out.mode == ANAL_NONLINEAR) return;
+  const int64_t slot = g.off[b] + coeff_offset(g.N, m) + k;
+  in[0] = out.forcing ? out.forcing[slot] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < kMaxStepCoef - 1; ++j)
+    in[1 + j] = (j < out.depth) ? out.hist[(int64_t)j * out.state_count + slot]
+                                : make_double2(0.0, 0.0);
+}
+
+__device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& out, int b, int m,
+                                          int k, double sx, double sy, const double2* in);
+
 __device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, int b, int m,
                                      int k, double sx, double sy) {
+  double2 in[kDegreeInputs];
+  load_degree_inputs(g, out, b, m, k, in);
+  finish_degree_from(g, out, b, m, k, sx, sy, in);
+}
+
+// As finish_degree, with the step-update inputs already loaded (load_degree_inputs).
+__device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& out, int b, int m,
+                                          int k, double sx, double sy, const double2* in) {
   const int l = m + k;
   const double lam = (double)l * (l + 1);
   double2 n = make_double2(0.0, 0.0);
@@ -128,11 +154,8 @@ __device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, 
     out.n_out[slot] = n;
     return;
   }
-  double2 rhs = make_double2(0.0, 0.0);
-  if (out.forcing) {
-    const double2 f = out.forcing[slot];
-    rhs = make_double2(out.h * f.x, out.h * f.y);
-  }
+  const double2 f = in[0];
+  double2 rhs = make_double2(out.h * f.x, out.h * f.y);
   rhs.x -= out.h * n.x;
   rhs.y -= out.h * n.y;
   double2 old[kMaxStepCoef];
@@ -141,7 +164,7 @@ __device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, 
   const int nold = out.depth;
 #pragma unroll
   for (int j = 0; j < kMaxStepCoef - 1; ++j)
-    if (j < nold) old[j] = out.hist[(int64_t)j * out.state_count + slot];
+    if (j < nold) old[j] = in[1 + j];
 #pragma unroll
   for (int j = 1; j < kMaxStepCoef; ++j) {
     if (j < out.ncoef) {
