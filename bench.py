@@ -361,6 +361,37 @@ def ensemble_timing(pkg, torch, steps=100, warmup=10):
     return out
 
 
+def ensemble_group_timing(pkg, torch, steps=100, warmup=10):
+    """The N=255 group of the mixed ensemble alone: 16 members (nu log-uniform in
+    [1e-5, 1e-3], member states 48..63 of the ensemble) in one context, member blocks
+    autotuned, steps replayed from the captured graph."""
+    import nse_inputs as I
+    nus = I.ensemble_viscosities(64)[48:]
+    specs = [(255, 0, float(nu)) for nu in nus]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = pkg.Sphere(specs, omega=2 * math.pi, dt=1e-3, graph=True, autotune=True,
+                       stream=stream)
+        h, f = s.new_history(), s.new_state()
+        for i in range(len(specs)):
+            h[0, s.member_slice(i)] = pkg.to_device(I.member_state(48 + i, 255))
+            f[s.member_slice(i)] = pkg.to_device(I.forcing(255))
+        s.step(h, f, 0, warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(h, f, warmup, steps)
+        s.sync()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        blocks = list(s.member_blocks(0))
+        finite = bool(torch.isfinite(torch.view_as_real(h)).all())
+        s.close()
+    return {"members": len(specs), "member_blocks": blocks,
+            "member_steps_per_s": round(len(specs) * steps / t, 1),
+            "ms_per_step": round(1e3 * t / steps, 4), "finite": finite}
+
+
 def example2_timing(pkg, torch, T=60.0, N=100, nu=1e-4, omega=1.0, rtol=1e-3):
     """The paper's Example 2 run: N = 100, nu = 1e-4, Omega = 1, seeded random initial
     flow (degrees 1..20), forcing f_{3,0}(t), integrated from t = 0 to T with the
@@ -459,6 +490,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-example2", action="store_true")
+    ap.add_argument("--ensemble-group-only", action="store_true",
+                    help="replace the mixed-truncation ensemble leg by its N=255 group alone "
+                         "(16 members in one context, one truncation group, no forked streams)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB read + 256 MiB write kernel, the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -556,7 +590,12 @@ def main():
         log("bench: T511 precision errors (200 steps)")
         extra.update({f"t511_{k}": v for k, v in precision_errors(pkg, torch, 511, 1e-5, 200).items()})
 
-    if not args.no_ensemble:
+    if not args.no_ensemble and args.ensemble_group_only:
+        log("bench: ensemble group 16 x N=255, 100 steps")
+        ens = ensemble_group_timing(pkg, torch)
+        extra["ensemble_group_n255"] = ens
+        log(f"bench: ensemble group {ens}")
+    elif not args.no_ensemble:
         log("bench: mixed-truncation ensemble, 64 members, 100 steps")
         ens = ensemble_timing(pkg, torch)
         extra["ensemble"] = ens
