@@ -430,6 +430,205 @@ __device__ void load_ring(double2* x0, double2* x1, double2* tw, const double2* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Nonlinear-mode ring kernel for M = 3 S, S = 128, 256 (the default grids of
+// N = 127 and 255). With k = k1 + 3 k2 and n = S n1 + n2 (k1, n1 < 3;
+// k2, n2 < S) the length-M transforms split into three S-point transforms and
+// one radix-3 pass:
+//   inverse: Y_k1 = IDFT_S(X[k1 + 3 .]),  x[S n1 + n2] = sum_k1 e^{2 pi i k1 n1/3} e^{2 pi i k1 n2/M} Y_k1[n2];
+//   forward: Z_k1[n2] = e^{-2 pi i k1 n2/M} sum_n1 q[S n1 + n2] e^{-2 pi i k1 n1/3},  Q[k1 + 3 k2] = DFT_S(Z_k1)[k2].
+// Each S-point transform belongs to one wave, which runs its Stockham stages
+// on its own LDS row: a wave's LDS accesses complete in program order, so the
+// stages need no workgroup barrier. The radix-3 passes of both directions and
+// the grid product meet in one pass (thread n2 holds the three grid points
+// S n1 + n2 of both paired fields), so the ring needs three workgroup barriers
+// (after the loads, after the six inverse transforms, after the fused pass)
+// where the radix-8/4/3 plan over the whole ring took about ten.
+template <int S> struct WavePlan { static constexpr int n = 0; static constexpr int r[1] = {0}; };
+template <> struct WavePlan<128> { static constexpr int n = 4; static constexpr int r[4] = {2, 4, 4, 4}; };
+template <> struct WavePlan<256> { static constexpr int n = 4; static constexpr int r[4] = {4, 4, 4, 4}; };
+
+__host__ __device__ constexpr int wave_row(int S) { return S + (S >> 4) + 1; }
+
+// exp(-2 pi i e / M), e < M, from the half table tw[0 .. M/2).
+template <int M>
+__device__ __forceinline__ double2 tw_full(const double2* tw, int e) {
+  constexpr int half = M / 2;
+  if (e < half) return tw[e];
+  const double2 t = tw[e - half];
+  return make_double2(-t.x, -t.y);
+}
+
+// One Stockham stage of radix R at stride NS over the S points of a wave's LDS
+// row x (in place: every lane reads its butterflies, then writes them); the
+// twiddles of length S are those of length M = 3 S at three times the index.
+// With STORE (the last forward stage, NS R = S) the outputs k2 = j + r NS go
+// to out[(k1 + 3 k2) * ostride] (scaled by c) for k1 + 3 k2 <= N instead.
+template <int R, int NS, int S, int SGN, bool STORE>
+__device__ __forceinline__ void wave_stage(double2* x, const double2* tw, int lane, double c,
+                                           double2* __restrict__ out, int64_t ostride, int k1,
+                                           int N) {
+  constexpr int M = 3 * S, span = S / R, MAXB = (span + 63) / 64;
+  constexpr int step = S / (NS * R), lg = ct_log2(NS);
+  double2 v[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = lane + 64 * b;
+    dst[b] = -1;
+    if (span % 64 == 0 || j < span) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = x[pad(j + r * span)];
+      const int k = j & (NS - 1), q = j >> lg;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw_full<M>(tw, 3 * r * k * step);
+          if (SGN > 0) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      butterfly<R>(v[b], (double)SGN);
+      dst[b] = q * NS * R + k;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    if (dst[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (STORE) {
+          const int m = k1 + 3 * (dst[b] + r * NS);
+          if (m <= N) out[(int64_t)m * ostride] = make_double2(c * v[b][r].x, c * v[b][r].y);
+        } else {
+          x[pad(dst[b] + r * NS)] = v[b][r];
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int S, int ST, int NS, int SGN, bool STORE_LAST>
+__device__ __forceinline__ void wave_fft(double2* x, const double2* tw, int lane, double c,
+                                         double2* __restrict__ out, int64_t ostride, int k1,
+                                         int N) {
+  if constexpr (ST < WavePlan<S>::n) {
+    constexpr int R = WavePlan<S>::r[ST];
+    constexpr bool last = ST + 1 == WavePlan<S>::n;
+    wave_stage<R, NS, S, SGN, STORE_LAST && last>(x, tw, lane, c, out, ostride, k1, N);
+    wave_fft<S, ST + 1, NS * R, SGN, STORE_LAST>(x, tw, lane, c, out, ostride, k1, N);
+  }
+}
+
+// Workgroup of NT >= max(S, 384) threads per ring: waves 0..5 hold the inverse
+// transforms Y_{a,k1} (a = 0: f0 + i f1, a = 1: f2 + i f3), threads n2 < S the
+// fused pass, waves 0..2 the forward transforms.
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
+  constexpr int M = 3 * S, PS = wave_row(S);
+  const int N = g.N, nlat = g.nlat;
+  const int lat = xcd_item(blockIdx.x, 8);
+  if (lat >= nlat) return;
+  const int b = blockIdx.y;
+  const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
+  extern __shared__ double2 lds[];
+  double2* tw = lds + 6 * PS;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* F0 = g.F + (int64_t)b * 4 * fstride + lat;
+
+  // loads: every spectrum value once (thread t: order m = t mod (N+1) of pair
+  // a = t / (N+1), both fields of the pair) and the twiddle half table, all
+  // requested before the first LDS write; X_a[m] = G^f_m + i G^f'_m goes to row
+  // 3a + m mod 3 at m / 3 and X_a[M - m] = conj(G^f_m) + i conj(G^f'_m) to row
+  // 3a + (M - m) mod 3 at (M - m) / 3
+  constexpr int KT = (M / 2 + NT - 1) / NT;
+  constexpr int KI = (2 * (S + 1) + NT - 1) / NT;  // N + 1 <= M / 3 + 1 = S + 1
+  const int n1 = N + 1;
+  double2 tv[KT], ga[KI], gb[KI];
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) tv[i] = g.tw[j];
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    ga[i] = gb[i] = make_double2(0.0, 0.0);
+    if (idx < 2 * n1) {
+      const int a = idx >= n1 ? 1 : 0, m = idx - a * n1;
+      const double2* Fa = F0 + (int64_t)(2 * a) * fstride + (int64_t)m * nlat;
+      ga[i] = Fa[0];
+      gb[i] = Fa[fstride];
+    }
+  }
+  const double x = g.mu[p];
+  const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
+  // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
+  // own mirror and is folded twice by the analysis
+  const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) tw[j] = tv[i];
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx < 2 * n1) {
+      const int a = idx >= n1 ? 1 : 0, m = idx - a * n1;
+      double2* rows = lds + 3 * a * PS;
+      if (m == 0) {
+        rows[0] = make_double2(ga[i].x, gb[i].x);
+      } else {
+        rows[(m % 3) * PS + pad(m / 3)] = make_double2(ga[i].x - gb[i].y, ga[i].y + gb[i].x);
+        const int k = M - m;
+        rows[(k % 3) * PS + pad(k / 3)] = make_double2(ga[i].x + gb[i].y, gb[i].x - ga[i].y);
+      }
+    }
+  }
+  // the zero band N < k < M - N of both arrays
+  for (int t = threadIdx.x; t < 2 * (M - 2 * N - 1); t += NT) {
+    const int a = t >= M - 2 * N - 1 ? 1 : 0;
+    const int k = N + 1 + t - a * (M - 2 * N - 1);
+    lds[(3 * a + k % 3) * PS + pad(k / 3)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (wave < 6) wave_fft<S, 0, 1, 1, false>(lds + wave * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
+  __syncthreads();
+  // fused pass at n2 = threadIdx.x: inverse twiddles and radix 3 of both pairs,
+  // the grid product at S n1 + n2, forward radix 3 and twiddles
+  for (int n2 = threadIdx.x; n2 < S; n2 += NT) {
+    const double2 w1 = tw_full<M>(tw, n2), w2 = tw_full<M>(tw, 2 * n2);
+    double2 y[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) y[a][k1] = lds[(3 * a + k1) * PS + pad(n2)];
+      y[a][1] = cmul(y[a][1], make_double2(w1.x, -w1.y));
+      y[a][2] = cmul(y[a][2], make_double2(w2.x, -w2.y));
+      butterfly<3>(y[a], 1.0);
+    }
+    double2 z[3];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1)
+      z[n1] = make_double2((y[0][n1].x * y[1][n1].x - y[0][n1].y * y[1][n1].y) * inv_sin2, 0.0);
+    butterfly<3>(z, -1.0);
+    z[1] = cmul(z[1], w1);
+    z[2] = cmul(z[2], w2);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) lds[k1 * PS + pad(n2)] = z[k1];
+  }
+  __syncthreads();
+  if (wave < 3) {
+    double2* Wl = g.W + (int64_t)b * (N + 1) * nlat + lat;  // W[b][m][lat]
+    wave_fft<S, 0, 1, -1, true>(lds + wave * PS, tw, lane, c, Wl, nlat, wave, N);
+  }
+}
+
 }  // namespace
 
 size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(M) + M / 2); }
@@ -705,9 +904,20 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
   });
 }
 
+size_t ring_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(6 * wave_row(M / 3) + M / 2); }
+
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
+  // the split kernel for M = 384 and 768 (T127, T255: ring 10.0 -> 9.4 us at
+  // T255); at M = 1536 its one-wave 512-point transforms are slower than the
+  // radix-8/8/8/3 plan over 1024 threads (ring 21.8 -> 23.6 us at T511)
+  if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
+    const size_t lds = ring_nl_lds_bytes(g.M);
+    if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384>), grid, dim3(384), lds, s, g);
+    else hipLaunchKernelGGL((k_ring_nl<256, 384>), grid, dim3(384), lds, s, g);
+    return hipGetLastError();
+  }
   const size_t lds = ring_lds_bytes(g.M);
   return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
     constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
