@@ -910,8 +910,10 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
                        hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
   // the split kernel for M = 384 and 768 (T127, T255: ring 10.0 -> 9.4 us at
-  // T255); at M = 1536 its one-wave 512-point transforms are slower than the
-  // radix-8/8/8/3 plan over 1024 threads (ring 21.8 -> 23.6 us at T511)
+  // T255). At M = 1536 the radix-8/8/8/3 plan over 1024 threads stays (21.8 us
+  // at T511): three one-wave 512-point transforms took 23.6 us, six 256-point
+  // ones with a radix-6 fused pass 26.8 us (twelve waves) and 25.8 us (six
+  // waves of two rows each, 52.7 KB of LDS: still two rings per CU)
   if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
     const size_t lds = ring_nl_lds_bytes(g.M);
     if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384>), grid, dim3(384), lds, s, g);
