@@ -295,6 +295,14 @@ typedef struct {
  * before it returns. */
 typedef double (*nse_forcing_fn)(void* user, double t);
 
+/* A forcing scale the device evaluates itself (nse_adaptive_begin_scheduled):
+ *   s(t) = before                                               for t <= t_on,
+ *   s(t) = amp cos(omega t + phase) exp(-decay (t - t_on))      for t > t_on,
+ * the switched-on, decaying oscillation of Example 2 (Section 5) as a family. */
+typedef struct {
+  double t_on, before, amp, omega, phase, decay;
+} nse_forcing_schedule;
+
 enum { NSE_ATTEMPT_ACCEPTED = 0, NSE_ATTEMPT_ERROR_FAIL = 1, NSE_ATTEMPT_NEWTON_FAIL = 2 };
 
 typedef struct {
@@ -313,7 +321,7 @@ typedef struct {
   int32_t reserved;
   int64_t accepted, error_failures, newton_failures;
   int64_t evaluations; /* nonlinear-term evaluations (hot-path chains)    */
-  int64_t waits;       /* host waits for the corrector norms              */
+  int64_t waits;       /* host waits (corrector norms, or attempt batches) */
   double wait_seconds; /* host time spent in those waits                  */
 } nse_adaptive_stats;
 
@@ -328,12 +336,26 @@ nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
                               const nse_adaptive_params* params, const double* forcing,
                               nse_forcing_fn fn, void* user);
 
+/* As nse_adaptive_begin with the forcing s(t) * forcing, s from `schedule`
+ * (NULL: s = 1). With no host callback to call, the controller (Newton test,
+ * error test, step and order choice) runs on the device after every corrector
+ * sweep, and nse_adaptive_advance enqueues captured attempt sequences whose
+ * kernels do nothing once the attempt has ended, waiting on the stream only
+ * between batches of attempts. nse_adaptive_begin with fn = NULL takes the same
+ * path; with a callback the controller runs on the host. */
+nse_status nse_adaptive_begin_scheduled(nse_ctx* ctx, const double* alpha0, double t0,
+                                        const nse_adaptive_params* params,
+                                        const double* forcing,
+                                        const nse_forcing_schedule* schedule);
+
 /* Integrates to t_end (>= the current time), ending exactly there, and writes
  * alpha(t_end) to the device state alpha_out (may be NULL); fills *stats if
- * non-NULL. Waits on the stream once per corrector sweep from the second on
- * and once per attempt. NSE_ERR_STATE before nse_adaptive_begin or when the
- * step falls below 16 eps |t|; NSE_ERR_NONFINITE if a norm is NaN/Inf (the
- * integration cannot continue; call nse_adaptive_begin again). */
+ * non-NULL. With a forcing callback (host controller) it waits on the stream
+ * once per corrector sweep from the second on and once per attempt; otherwise
+ * once per batch of attempts (stats->waits counts the waits either way).
+ * NSE_ERR_STATE before nse_adaptive_begin or when the step falls below
+ * 16 eps |t|; NSE_ERR_NONFINITE if a norm is NaN/Inf (the integration cannot
+ * continue; call nse_adaptive_begin again). */
 nse_status nse_adaptive_advance(nse_ctx* ctx, double t_end, double* alpha_out,
                                 nse_adaptive_stats* stats);
 

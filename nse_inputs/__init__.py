@@ -215,6 +215,13 @@ def example2_force(t: float) -> float:
     return 1.0 if t <= 10.0 else float(np.cos(np.pi * t / 5.0) * np.exp(-(t - 10.0) / 5.0))
 
 
+def example2_schedule() -> dict:
+    """The same f_{3,0}(t) as parameters of the switched-on decaying oscillation
+    s(t) = before (t <= t_on), amp cos(omega t + phase) exp(-decay (t - t_on))."""
+    return {"t_on": 10.0, "before": 1.0, "amp": 1.0, "omega": np.pi / 5.0, "phase": 0.0,
+            "decay": 0.2}
+
+
 def as_real_view(alpha: np.ndarray) -> np.ndarray:
     """Interleaved (re, im) float64 view of a complex128 array."""
     return np.ascontiguousarray(alpha).view(np.float64)

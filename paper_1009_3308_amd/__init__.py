@@ -38,7 +38,8 @@ EXPORTS = (
     "nse_nonlinear_adjoint", "nse_step_adjoint", "nse_synthesize", "nse_legendre_values",
     "nse_sync", "nse_status_string", "nse_last_error", "nse_profile_enable", "nse_profile_read",
     "nse_analyze_velocity", "nse_get_member_blocks", "nse_set_member_blocks",
-    "nse_adaptive_begin", "nse_adaptive_advance", "nse_adaptive_log",
+    "nse_adaptive_begin", "nse_adaptive_begin_scheduled", "nse_adaptive_advance",
+    "nse_adaptive_log",
     "nse_energy_spectrum", "nse_synthesize_psi", "nse_inertial_manifold",
     "nse_nonlinear_adjoint_noalloc",
 )
@@ -87,6 +88,14 @@ class AdaptiveStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class ForcingSchedule(ctypes.Structure):
+    """Forcing scale evaluated on the device: s(t) = before for t <= t_on, else
+    amp cos(omega t + phase) exp(-decay (t - t_on))."""
+    _fields_ = [("t_on", ctypes.c_double), ("before", ctypes.c_double),
+                ("amp", ctypes.c_double), ("omega", ctypes.c_double),
+                ("phase", ctypes.c_double), ("decay", ctypes.c_double)]
+
+
 FORCING_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p, ctypes.c_double)
 
 _lib = None
@@ -126,6 +135,9 @@ def lib():
         "nse_profile_read": (st, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
         "nse_adaptive_begin": (st, [vp, dp, ctypes.c_double, ctypes.POINTER(AdaptiveParams), dp,
                                     FORCING_FN, vp]),
+        "nse_adaptive_begin_scheduled": (st, [vp, dp, ctypes.c_double,
+                                              ctypes.POINTER(AdaptiveParams), dp,
+                                              ctypes.POINTER(ForcingSchedule)]),
         "nse_adaptive_advance": (st, [vp, ctypes.c_double, dp, ctypes.POINTER(AdaptiveStats)]),
         "nse_adaptive_log": (st, [vp, ctypes.POINTER(AdaptiveRecord), i64,
                                   ctypes.POINTER(i64)]),
@@ -387,8 +399,10 @@ class Sphere:
         """Starts a variable-order, variable-step NDF integration at (t0, alpha0).
 
         forcing: None (zero), a state tensor (constant in time), a callable
-        t -> state tensor (evaluated on the context stream at every time level), or
-        a pair (state tensor F, callable t -> float s) for f(t) = s(t) F.
+        t -> state tensor (evaluated on the context stream at every time level), a
+        pair (state tensor F, callable t -> float s) for f(t) = s(t) F, or a pair
+        (F, ForcingSchedule) whose scale the device evaluates. Without a callback
+        the step and order control runs on the device.
         """
         import torch
         self._ad_error = None
@@ -404,6 +418,17 @@ class Sphere:
                     return 0.0
             return FORCING_FN(cb)
 
+        p = AdaptiveParams(float(rtol), float(atol), float(h0), float(hmax), int(max_order),
+                           int(max_newton))
+        a0 = _ptr(alpha0, torch.complex128, self.state_count, "alpha0")
+        if isinstance(forcing, tuple) and isinstance(forcing[1], ForcingSchedule):
+            self._ad_fbuf, sched = forcing
+            self._ad_fn = None
+            fptr = _ptr(self._ad_fbuf, torch.complex128, self.state_count, "forcing")
+            _check(lib().nse_adaptive_begin_scheduled(self._handle(), a0, float(t0),
+                                                      ctypes.byref(p), fptr,
+                                                      ctypes.byref(sched)), self._h)
+            return
         if isinstance(forcing, tuple):
             self._ad_fbuf, scale = forcing
             fn = guarded(lambda t: float(scale(t)))
@@ -423,11 +448,8 @@ class Sphere:
             self._ad_fbuf = forcing
             fptr = _ptr(forcing, torch.complex128, self.state_count, "forcing")
         self._ad_fn = fn  # the library keeps the pointer
-        p = AdaptiveParams(float(rtol), float(atol), float(h0), float(hmax), int(max_order),
-                           int(max_newton))
-        st = lib().nse_adaptive_begin(
-            self._handle(), _ptr(alpha0, torch.complex128, self.state_count, "alpha0"),
-            float(t0), ctypes.byref(p), fptr, fn, None)
+        st = lib().nse_adaptive_begin(self._handle(), a0, float(t0), ctypes.byref(p), fptr, fn,
+                                      None)
         self._raise_callback_error()
         _check(st, self._h)
 

@@ -46,8 +46,9 @@ namespace {
 
 constexpr int kOtfDeg = kButterfly;  // degrees per wave
 
-template <typename TT, int R>
+template <typename TT, int R, bool NDF>
 __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   const int N = g.N, nh = g.nh;
   const int ntile = (N + 1 + 63) / 64;
   const int item = xcd_item(blockIdx.x, 4 * ntile);
@@ -160,13 +161,23 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     }
   }
   lane_butterfly16(sr, si, lane);
-  if ((lane & 3) != 0) return;
   const int j = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) +
                 ((lane >> 2) & 1);
   const int k = kt + j0 + j;
-  if (k > N - m) return;
-  finish_degree_from(g, out, b, m, k, (double)sr[0], (double)si[0],
-                     pre + (k - kt) * kDegreeInputs);
+  if constexpr (NDF) {
+    // every lane stays for the wave's norm maxima
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if ((lane & 3) == 0 && k <= N - m)
+      finish_degree_from<true>(g, out, b, m, k, (double)sr[0], (double)si[0],
+                               pre + (k - kt) * kDegreeInputs, v);
+    const int copy = ((blockIdx.y * gridDim.x + blockIdx.x) * kAnalWaves + wave) % kNdfSpread;
+    wave_max4_atomic(v, out.nrow + copy * kNdfSpreadStride);
+  } else {
+    if ((lane & 3) != 0) return;
+    if (k > N - m) return;
+    finish_degree_from(g, out, b, m, k, (double)sr[0], (double)si[0],
+                       pre + (k - kt) * kDegreeInputs);
+  }
 }
 
 }  // namespace
@@ -175,16 +186,16 @@ size_t analysis_otf_lds_bytes(int nh) {
   return sizeof(double2) * (size_t)(2 * nh + 64 + 64 * kDegreeInputs);
 }
 
-template <typename TT>
+template <typename TT, bool NDF>
 hipError_t launch_analysis_otf(dim3 grid, dim3 block, size_t lds, hipStream_t s,
                                const GroupView& g, const AnalOutput& out) {
   switch ((g.nh + 63) / 64) {
-    case 1: hipLaunchKernelGGL((k_analysis_otf<TT, 1>), grid, block, lds, s, g, out); break;
-    case 2: hipLaunchKernelGGL((k_analysis_otf<TT, 2>), grid, block, lds, s, g, out); break;
-    case 3: hipLaunchKernelGGL((k_analysis_otf<TT, 3>), grid, block, lds, s, g, out); break;
-    case 4: hipLaunchKernelGGL((k_analysis_otf<TT, 4>), grid, block, lds, s, g, out); break;
-    case 5: hipLaunchKernelGGL((k_analysis_otf<TT, 5>), grid, block, lds, s, g, out); break;
-    default: hipLaunchKernelGGL((k_analysis_otf<TT, 6>), grid, block, lds, s, g, out); break;
+    case 1: hipLaunchKernelGGL((k_analysis_otf<TT, 1, NDF>), grid, block, lds, s, g, out); break;
+    case 2: hipLaunchKernelGGL((k_analysis_otf<TT, 2, NDF>), grid, block, lds, s, g, out); break;
+    case 3: hipLaunchKernelGGL((k_analysis_otf<TT, 3, NDF>), grid, block, lds, s, g, out); break;
+    case 4: hipLaunchKernelGGL((k_analysis_otf<TT, 4, NDF>), grid, block, lds, s, g, out); break;
+    case 5: hipLaunchKernelGGL((k_analysis_otf<TT, 5, NDF>), grid, block, lds, s, g, out); break;
+    default: hipLaunchKernelGGL((k_analysis_otf<TT, 6, NDF>), grid, block, lds, s, g, out); break;
   }
   return hipGetLastError();
 }
@@ -194,9 +205,12 @@ hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_
   const int ntile = (g.N + 1 + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
   const size_t lds = analysis_otf_lds_bytes(g.nh);
+  const bool ndf = out.mode == ANAL_NDF;
   if (g.precision == NSE_PREC_FP32)
-    return launch_analysis_otf<float>(grid, block, lds, s, g, out);
-  return launch_analysis_otf<double>(grid, block, lds, s, g, out);
+    return ndf ? launch_analysis_otf<float, true>(grid, block, lds, s, g, out)
+               : launch_analysis_otf<float, false>(grid, block, lds, s, g, out);
+  return ndf ? launch_analysis_otf<double, true>(grid, block, lds, s, g, out)
+             : launch_analysis_otf<double, false>(grid, block, lds, s, g, out);
 }
 
 }  // namespace nse

@@ -108,6 +108,7 @@ size_t split_panel_lp_lds_bytes(int N) { return sizeof(double2) * (size_t)(5 * N
 // which only the four degrees of the column's parity are stored (bf16x4).
 __global__ __launch_bounds__(kLpThreads) void k_split_panel_lp(GroupView g, SynthInput in,
                                                                int mode) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   const int N = g.N;
   const int m = blockIdx.x, b = blockIdx.y;
   const int L = N + 2 - m;
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(kLpThreads) void k_split_panel_lp(GroupView g, Synt
 }
 
 __global__ __launch_bounds__(kLpThreads) void k_synthesis_lp(GroupView g, SynthInput in, int mode) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (nh + 63) / 64;
   const int m = blockIdx.x / ntile;
@@ -225,6 +227,7 @@ size_t analysis_lp_lds_bytes(int nh) {
 }
 
 __global__ __launch_bounds__(kLpThreads) void k_analysis_lp(GroupView g, AnalOutput out) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   const int N = g.N, nh = g.nh;
   const int ntile = (N + 1 + 63) / 64;
   const int item = xcd_item(blockIdx.x, 4 * ntile);

@@ -41,6 +41,7 @@ __device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
 
 template <int B>
 __global__ __launch_bounds__(kMbThreads) void k_analysis_mb(GroupView g, AnalOutput out) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   static_assert(2 * B <= 16, "one 16-column block: (member, re/im)");
   constexpr int NW = (64 * B + kMbThreads - 1) / kMbThreads;  // fold items per thread
   __shared__ double wf[2][64][16];  // folded ring spectra of a 64-latitude chunk: [parity][p][col]
@@ -156,6 +157,7 @@ constexpr int kChunkS = 32;
 
 template <int B>
 __global__ __launch_bounds__(kMbThreads) void k_synthesis_mb(GroupView g, SynthInput in) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int NC = 8 * B;            // panel columns per parity
   constexpr int NCB = NC / 16;         // 16-column blocks
   constexpr int WP = NC + 2;           // LDS row stride (doubles), padded against bank conflicts

@@ -1,8 +1,10 @@
 // Device side of the adaptive NDF integrator (Section 4.2, eq. (ode_disc) with
 // orders 1..5, written in backward differences at a quasi-constant step).
-// Both kernels are elementwise over the state; the nonlinear term between them
-// comes from the synthesis / ring / analysis chain.
-#include "nse_internal.h"
+// k_ndf_prepare and k_ndf_correct are elementwise over the state; the nonlinear
+// term between them comes from the synthesis / ring / analysis chain. On a
+// device-controlled run k_ndf_decide runs the controller of ndf_control.h
+// after each sweep and opens the next attempt.
+#include "ndf_control.h"
 
 namespace nse {
 
@@ -11,33 +13,87 @@ namespace {
 __device__ inline double2 zero2() { return make_double2(0.0, 0.0); }
 __device__ inline double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
 
+// The control block in LDS: copied in by the whole workgroup, worked on by
+// thread 0, copied back.
+constexpr int kCtlWords = sizeof(NdfCtl) / sizeof(unsigned long long);
+static_assert(sizeof(NdfCtl) % sizeof(unsigned long long) == 0, "8-byte words");
+
+__device__ inline void ctl_load(NdfCtl* sc, const NdfCtl* c) {
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(c);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(sc);
+  for (int i = threadIdx.x; i < kCtlWords; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+}
+__device__ inline void ctl_store(NdfCtl* c, const NdfCtl* sc) {
+  __syncthreads();
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sc);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(c);
+  for (int i = threadIdx.x; i < kCtlWords; i += blockDim.x) dst[i] = src[i];
+}
+
+// Runs the controller after sweep slot `slot` (ndf_decide) if that slot ran:
+// the norms of the sweep, the next slot's gate or the attempt's record (to the
+// log ring) and the opening of the next attempt.
+__global__ __launch_bounds__(64) void k_ndf_decide(NdfCtl* c, const unsigned long long* spread_row,
+                                                   int slot, nse_adaptive_record* log,
+                                                   nse_forcing_schedule sched) {
+  static_assert(kNdfSpread == 64, "one copy per lane");
+  if (__hip_atomic_load(&c->gates[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  __shared__ NdfCtl sc;
+  // the sweep's norms: the maximum over the spread copies (lane t: copy t)
+  double v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    v[q] = __longlong_as_double((long long)spread_row[threadIdx.x * kNdfSpreadStride + q]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o, 64));
+  ctl_load(&sc, c);
+  if (threadIdx.x == 0) {
+    double row[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) row[q] = sqrt(v[q]);
+    if (ndf_decide(sc, slot, row, sched) == NDF_ENDED) log[(sc.nlog - 1) % kNdfLogCap] = sc.rec;
+  }
+  ctl_store(c, &sc);
+}
+
 // Accepted-step update of the differences, rescaling to a new step and the
 // predictor of the next attempt, one state slot per thread.
 __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
+  const NdfCtl* ctl = a.ctl;
+  if (ctl && __hip_atomic_load(&ctl->open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    return;
   if (blockIdx.x == 0 && (int)threadIdx.x < a.nnorms) a.norms[threadIdx.x] = 0ull;
   if (blockIdx.x == 0 && a.done && (int)threadIdx.x < a.nnorms / 4) a.done[threadIdx.x] = 0u;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.spread)
+    for (int64_t w = s; w < a.spread_words; w += (int64_t)gridDim.x * blockDim.x) a.spread[w] = 0ull;
   if (s >= a.S) return;
+  const int accept = ctl ? ctl->prep_accept : a.accept;
+  const int transform = ctl ? ctl->prep_transform : a.transform;
+  const int predict = ctl ? ctl->prep_predict : a.predict;
+  const int k = ctl ? ctl->prep_k : a.k;
+  const auto R = ctl ? ctl->prepR : a.R;
   double2 D[kNdfDepth];
 #pragma unroll
   for (int j = 0; j < kNdfDepth; ++j) D[j] = (j < a.depth) ? a.D[(int64_t)j * a.S + s] : zero2();
-  if (a.accept) {
+  if (accept) {
     // nabla^{k+1} y_{n+1} = d, nabla^{k+2} y_{n+1} = d - nabla^{k+1} y_n,
     // nabla^j y_{n+1} = nabla^j y_n + nabla^{j+1} y_{n+1}
-    const int k = a.k_acc;
-    const double2 d = a.dacc[s];
+    const int ka = ctl ? ctl->prep_k_acc : a.k_acc;
+    const double2 d = ctl ? a.dsel[ctl->prep_dsel][s] : a.dacc[s];
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j)
-      if (j == k + 2) D[j] = make_double2(d.x - D[j - 1].x, d.y - D[j - 1].y);
+      if (j == ka + 2) D[j] = make_double2(d.x - D[j - 1].x, d.y - D[j - 1].y);
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j)
-      if (j == k + 1) D[j] = d;
+      if (j == ka + 1) D[j] = d;
 #pragma unroll
     for (int j = kNdfDepth - 2; j >= 0; --j)
-      if (j <= k) D[j] = make_double2(D[j].x + D[j + 1].x, D[j].y + D[j + 1].y);
+      if (j <= ka) D[j] = make_double2(D[j].x + D[j + 1].x, D[j].y + D[j + 1].y);
   }
-  if (a.transform) {
-    const int k = a.k;
+  if (transform) {
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j) {
       double2 v = zero2();
@@ -45,23 +101,23 @@ __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
 #pragma unroll
         for (int i = 0; i <= kNdfMaxOrder; ++i)
           if (i >= j && i <= k) {
-            v.x += a.R[j][i] * D[i].x;
-            v.y += a.R[j][i] * D[i].y;
+            v.x += R[j][i] * D[i].x;
+            v.y += R[j][i] * D[i].y;
           }
       }
       D[j] = v;  // rows are computed from D[i >= j] before D[j] is replaced
     }
   }
-  if (a.accept || a.transform) {
+  if (accept || transform) {
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j)
       if (j < a.depth) a.D[(int64_t)j * a.S + s] = D[j];
   }
-  if (a.predict) {
+  if (predict) {
     double2 y = D[0], p = zero2();
 #pragma unroll
     for (int j = 1; j <= kNdfMaxOrder; ++j)
-      if (j <= a.k) {
+      if (j <= k) {
         y.x += D[j].x;
         y.y += D[j].y;
         p.x += a.gam[j] * D[j].x;
@@ -71,9 +127,6 @@ __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
     a.psi[s] = p;
   }
 }
-
-// max that keeps a NaN operand (fmax would drop it)
-__device__ inline double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
 
 // Max over the block of four non-negative values, then one atomic per value.
 // Non-negative IEEE doubles order like their bit patterns, and a NaN sorts
@@ -119,6 +172,13 @@ __device__ inline void publish_norms(const NdfArgs& a) {
 // block (m, degree chunk, member). The four weighted norms use
 // wt = max(|y_n|, |y_i|, atol/rtol) per complex coefficient (squared here).
 __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
+  const NdfCtl* ctl = a.ctl;
+  if (ctl &&
+      __hip_atomic_load(&ctl->gates[a.sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    return;
+  const int ak_k = ctl ? ctl->k : a.k;
+  const double h = ctl ? ctl->h : a.h;
+  const double fscale = ctl ? ctl->fscale : a.fscale;
   const int N = g.N;
   const int m = blockIdx.x, b = blockIdx.z;
   const int kk = blockIdx.y * blockDim.x + threadIdx.x;
@@ -129,7 +189,7 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
     const double Lam = g.nu[b] * ((double)l * (l + 1));
     const double2 n = a.n[s];
     double2 f = a.f ? a.f[s] : zero2();
-    f = make_double2(a.fscale * f.x, a.fscale * f.y);
+    f = make_double2(fscale * f.x, fscale * f.y);
     const double2 D0 = a.D[s];
     if (a.mode == NDF_RHS) {
       double2 F = make_double2(f.x - Lam * D0.x - n.x, f.y - Lam * D0.y - n.y);
@@ -139,10 +199,10 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
       v[0] = abs2(F) / fmax(abs2(D0), a.thr2);
     } else {
       const double2 y0 = a.y0[s], ps = a.psi[s];
-      const double hL = a.h * Lam;
-      const double den = a.ak + hL;
-      double2 d = make_double2((a.h * (f.x - n.x) - hL * y0.x - ps.x) / den,
-                               (a.h * (f.y - n.y) - hL * y0.y - ps.y) / den);
+      const double hL = h * Lam;
+      const double den = (ctl ? ndf_alpha(ak_k) : a.ak) + hL;
+      double2 d = make_double2((h * (f.x - n.x) - hL * y0.x - ps.x) / den,
+                               (h * (f.y - n.y) - hL * y0.y - ps.y) / den);
       if (l == 0) d = zero2();
       if (m == 0) d.y = 0.0;
       const double2 y = make_double2(y0.x + d.x, y0.y + d.y);
@@ -152,18 +212,18 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
       const double wt2 = fmax(fmax(abs2(D0), abs2(y)), a.thr2);
       v[0] = abs2(make_double2(d.x - dp.x, d.y - dp.y)) / wt2;
       v[1] = abs2(d) / wt2;
-      if (a.k > 1) {
-        const double2 Dk = a.D[(int64_t)a.k * a.S + s];
+      if (ak_k > 1) {
+        const double2 Dk = a.D[(int64_t)ak_k * a.S + s];
         v[2] = abs2(make_double2(Dk.x + d.x, Dk.y + d.y)) / wt2;
       }
-      if (a.k < a.kmax) {
-        const double2 Dk1 = a.D[(int64_t)(a.k + 1) * a.S + s];
+      if (ak_k < a.kmax) {
+        const double2 Dk1 = a.D[(int64_t)(ak_k + 1) * a.S + s];
         v[3] = abs2(make_double2(d.x - Dk1.x, d.y - Dk1.y)) / wt2;
       }
     }
   }
-  block_max4(v, a.nrow);
-  if (a.publish) publish_norms(a);
+  block_max4(v, ctl ? a.nrow + (blockIdx.x % kNdfSpread) * kNdfSpreadStride : a.nrow);
+  if (!ctl && a.publish) publish_norms(a);
 }
 
 }  // namespace
@@ -171,6 +231,13 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
 hipError_t launch_ndf_prepare(const NdfArgs& a, hipStream_t s) {
   const int64_t blocks = (a.S + 255) / 256;
   hipLaunchKernelGGL(k_ndf_prepare, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ndf_decide(NdfCtl* c, const unsigned long long* spread_row, int slot,
+                             nse_adaptive_record* log, const nse_forcing_schedule& sched,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_ndf_decide, dim3(1), dim3(64), 0, s, c, spread_row, slot, log, sched);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 #include <tuple>
 #include <vector>
 
+#include "ndf_control.h"
 #include "nse_internal.h"
 
 using namespace nse;
@@ -147,26 +148,29 @@ struct nse_ctx {
   std::vector<hipEvent_t> event_pool;
   int64_t prof_count[NSE_KERNEL_KINDS] = {0, 0, 0};
   double prof_ms[NSE_KERNEL_KINDS] = {0, 0, 0};
-  // adaptive NDF integrator: controller state on the host, differences and
-  // sweep buffers on the device
+  // adaptive NDF integrator: controller state (ndf_control.h) mirrored between
+  // host and device, differences and sweep buffers on the device
   struct Adaptive {
     bool active = false, started = false;
     nse_adaptive_params p{};
     const double2* forcing = nullptr;
     nse_forcing_fn fn = nullptr;
     void* user = nullptr;
-    double t = 0.0, h = 0.0, fnorm = 0.0;
-    double fscale = 1.0;  // s(t) of the forcing at the level being computed
-    int k = 1, nconst = 0;
-    // work for the next k_ndf_prepare launch: the accepted correction, then a
-    // rescaling of D[0..tk]
-    bool pend_accept = false, pend_transform = false;
-    int pend_k = 0, pend_tk = 0;
-    const double2* pend_d = nullptr;
-    double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1] = {};
-    nse_adaptive_stats stats{};
+    nse_forcing_schedule sched{};  // device-evaluated forcing scale (no callback)
+    double fnorm = 0.0;
+    NdfCtl c{};  // authoritative between nse_adaptive_* calls
+    int64_t waits = 0;
+    double wait_seconds = 0.0;
     std::vector<nse_adaptive_record> log;
   } ad;
+  NdfCtl* d_ctl = nullptr;               // device copy during device-controlled runs
+  NdfCtl* h_ctl = nullptr;               // pinned staging of its copies
+  nse_adaptive_record* d_log = nullptr;  // [kNdfLogCap] ring of attempt records
+  unsigned long long* d_spread = nullptr;  // [kMaxNewton][kNdfSpreadRow] sweep norm copies
+  hipGraph_t ad_graph = nullptr;         // captured attempt sequence
+  hipGraphExec_t ad_exec = nullptr;
+  hipStream_t cap_stream = nullptr;      // private stream it is captured on (the
+                                         // context stream may be the null stream)
   double2* d_diag = nullptr;  // inertial manifold: band-limited input, its nonlinear term
   double2* d_ndf = nullptr;  // D [depth][S], then y0, psi, y, dA, dB, n (each S)
   int ndf_depth = 0;
@@ -210,15 +214,6 @@ nse_status hip_fail(nse_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
   } while (0)
 
-// kappa_p of the NDF_p formulas (Section 4.2, after eq. (ode_disc)).
-const double kKappa[6] = {0.0, -0.1850, -1.0 / 9.0, -0.0823, -0.0415, 0.0};
-
-double binom(int n, int k) {
-  double r = 1.0;
-  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-  return r;
-}
-
 // Coefficients of sum_{m=1}^{q} (1/m) nabla^m y_{n+1} - kappa_q gamma_q nabla^{q+1} y_{n+1}
 // (eq. (ode_disc)) as c_0..c_{len-1} of sum_j c_j y_{n+1-j}, and the
 // predictor sum_{j=0}^{d} nabla^j y_n = sum_i pi_i y_{n-i} for step index k:
@@ -226,21 +221,21 @@ double binom(int n, int k) {
 // predictor degree d = min(q, k).
 void step_scheme(int p, int64_t k, std::vector<double>& c, std::vector<double>& pi) {
   const int q = (int)std::min<int64_t>(p, k + 1);
-  const bool kap = (k >= q) && kKappa[q] != 0.0;
+  const bool kap = (k >= q) && ndf_kappa(q) != 0.0;
   const int len = kap ? q + 2 : q + 1;
   c.assign(len, 0.0);
   for (int m = 1; m <= q; ++m)
-    for (int j = 0; j <= m; ++j) c[j] += ((j & 1) ? -1.0 : 1.0) * binom(m, j) / m;
+    for (int j = 0; j <= m; ++j) c[j] += ((j & 1) ? -1.0 : 1.0) * ndf_binom(m, j) / m;
   if (kap) {
     double gamma = 0.0;
     for (int j = 1; j <= q; ++j) gamma += 1.0 / j;
     for (int j = 0; j <= q + 1; ++j)
-      c[j] -= kKappa[q] * gamma * ((j & 1) ? -1.0 : 1.0) * binom(q + 1, j);
+      c[j] -= ndf_kappa(q) * gamma * ((j & 1) ? -1.0 : 1.0) * ndf_binom(q + 1, j);
   }
   const int d = (int)std::min<int64_t>(q, k);
   pi.assign(d + 1, 0.0);
   for (int j = 0; j <= d; ++j)
-    for (int i = 0; i <= j; ++i) pi[i] += ((i & 1) ? -1.0 : 1.0) * binom(j, i);
+    for (int i = 0; i <= j; ++i) pi[i] += ((i & 1) ? -1.0 : 1.0) * ndf_binom(j, i);
 }
 
 int min_nlat(int N) { return (3 * N + 2 + 1) / 2; }
@@ -526,7 +521,8 @@ nse_status ensure_aux_streams(nse_ctx* c) {
 // runs on the context stream and every other group on its own stream forked
 // from it and joined back, so that the chains of different truncations overlap
 // on the GPU (inside a captured graph the fork and the join become edges).
-nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out) {
+nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out,
+                         const int* gate = nullptr) {
   const bool fork = !c->profiling && c->groups.size() > 1;
   if (fork) {
     nse_status s = ensure_aux_streams(c);
@@ -537,7 +533,8 @@ nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out
   }
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
     auto& g = c->groups[gi];
-    const GroupView v = g.view();
+    GroupView v = g.view();
+    v.gate = gate;
     if (fork) {
       hipStream_t st = gi ? c->aux[gi - 1] : c->stream;
       NSE_HIP(c, launch_synth_any(v, in, SYNTH_NONLINEAR, st));
@@ -662,40 +659,11 @@ nse_status enqueue_nonlinear_adjoint(nse_ctx* c, SynthInput in, const double2* n
 }
 
 // ---------------------------------------------------------------------------
-// Adaptive NDF integrator (host controller).
+// Adaptive NDF integrator. The controller (ndf_control.h) runs on the host when
+// a forcing callback has to be called per time level, else on the device.
 
-constexpr int kMaxNewton = 8;
-
-double ndf_gamma(int k) {
-  double g = 0.0;
-  for (int j = 1; j <= k; ++j) g += 1.0 / j;
-  return g;
-}
-// (1 - kappa_k) gamma_k and kappa_k gamma_k + 1/(k+1)
-double ndf_alpha(int k) { return (1.0 - kKappa[k]) * ndf_gamma(k); }
-double ndf_error_constant(int k) { return kKappa[k] * ndf_gamma(k) + 1.0 / (k + 1); }
-
-// Rescaling of backward differences from spacing h to rho h, order k:
-// D_new[j] = sum_i R[j][i] D[i]. The interpolant through y_n .. y_{n-k} is
-// p(t_n + s h) = sum_i c_i(s) D[i], c_i(s) = prod_{q<i} (s + q) / (q + 1)
-// (Newton's backward form); the new differences are
-// nabla'^j = sum_{q<=j} (-1)^q C(j, q) p(t_n - q rho h).
-void step_change(int k, double rho, double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1]) {
-  for (int j = 0; j <= kNdfMaxOrder; ++j)
-    for (int i = 0; i <= kNdfMaxOrder; ++i) R[j][i] = 0.0;
-  for (int j = 0; j <= k; ++j) {
-    for (int i = j; i <= k; ++i) {
-      double acc = 0.0;
-      for (int q = 0; q <= j; ++q) {
-        const double s = -q * rho;
-        double c = 1.0;
-        for (int t = 0; t < i; ++t) c *= (s + t) / (t + 1);
-        acc += ((q & 1) ? -1.0 : 1.0) * binom(j, q) * c;
-      }
-      R[j][i] = acc;
-    }
-  }
-}
+constexpr int kAttemptsPerGraph = 4;     // attempts in one captured sequence
+constexpr int kMaxGraphsPerBatch = 32;   // sequences enqueued between two waits
 
 nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
   if (c->d_ndf && c->ndf_depth == depth) return NSE_OK;
@@ -712,7 +680,21 @@ nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
     std::memset(c->h_pub, 0, sizeof(unsigned long long) * (4 * kMaxNewton + 1));
     NSE_HIP(c, hipHostGetDevicePointer((void**)&c->d_pub, c->h_pub, 0));
   }
+  if (!c->d_ctl) {
+    NSE_HIP(c, hipMalloc((void**)&c->d_ctl, sizeof(NdfCtl)));
+    NSE_HIP(c, hipHostMalloc((void**)&c->h_ctl, sizeof(NdfCtl), hipHostMallocDefault));
+    NSE_HIP(c, hipMalloc((void**)&c->d_log, sizeof(nse_adaptive_record) * kNdfLogCap));
+    NSE_HIP(c, hipMalloc((void**)&c->d_spread,
+                         sizeof(unsigned long long) * kMaxNewton * kNdfSpreadRow));
+  }
   return NSE_OK;
+}
+
+void drop_attempt_graph(nse_ctx* c) {
+  if (c->ad_exec) (void)hipGraphExecDestroy(c->ad_exec);
+  if (c->ad_graph) (void)hipGraphDestroy(c->ad_graph);
+  c->ad_exec = nullptr;
+  c->ad_graph = nullptr;
 }
 
 double2* ndf_buf(nse_ctx* c, int i) {  // 0 y0, 1 psi, 2 y, 3 dA, 4 dB, 5 n
@@ -737,8 +719,8 @@ nse_status read_norms(nse_ctx* c, int rows, double out[][4]) {
     }
   }
   std::atomic_thread_fence(std::memory_order_acquire);
-  c->ad.stats.waits++;
-  c->ad.stats.wait_seconds +=
+  c->ad.waits++;
+  c->ad.wait_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   volatile unsigned long long* pub = c->h_pub;
   for (int r = 0; r < rows; ++r)
@@ -762,58 +744,31 @@ NdfArgs ndf_args(nse_ctx* c) {
   a.norms = c->d_norms;
   a.nnorms = 4 * kMaxNewton;
   a.done = reinterpret_cast<unsigned int*>(c->d_norms + 4 * kMaxNewton);
-  return a;
-}
-
-// k_ndf_prepare with the pending accept / rescale and, if `predict`, the
-// predictor of order ad.k; clears the sweep norms.
-nse_status ndf_prepare(nse_ctx* c, bool predict) {
-  auto& ad = c->ad;
-  NdfArgs a = ndf_args(c);
-  a.accept = ad.pend_accept;
-  a.k_acc = ad.pend_k;
-  a.dacc = ad.pend_d;
-  a.transform = ad.pend_transform;
-  a.k = ad.pend_transform ? ad.pend_tk : ad.k;
-  std::memcpy(a.R, ad.R, sizeof(a.R));
-  a.predict = predict;
-  if (predict) a.k = ad.k;
   for (int j = 0; j <= kNdfMaxOrder; ++j) a.gam[j] = ndf_gamma(j);
   a.y0 = ndf_buf(c, 0);
   a.psi = ndf_buf(c, 1);
+  return a;
+}
+
+// k_ndf_prepare from the prepare snapshot of the host's controller state
+// (clears the sweep norms).
+nse_status ndf_prepare_host(nse_ctx* c) {
+  const NdfCtl& k = c->ad.c;
+  NdfArgs a = ndf_args(c);
+  a.accept = k.prep_accept;
+  a.k_acc = k.prep_k_acc;
+  a.dacc = ndf_buf(c, 3 + k.prep_dsel);
+  a.transform = k.prep_transform;
+  a.k = k.prep_k;
+  std::memcpy(a.R, k.prepR, sizeof(a.R));
+  a.predict = k.prep_predict;
   NSE_HIP(c, launch_ndf_prepare(a, c->stream));
-  ad.pend_accept = ad.pend_transform = false;
   return NSE_OK;
 }
 
-// Changes h (and rescales D[0..k] at the next prepare), composing with a
-// rescaling that is still pending.
-void ndf_rescale(nse_ctx* c, double h_new) {
-  auto& ad = c->ad;
-  double R[kNdfMaxOrder + 1][kNdfMaxOrder + 1];
-  step_change(ad.k, h_new / ad.h, R);
-  if (ad.pend_transform) {
-    double P[kNdfMaxOrder + 1][kNdfMaxOrder + 1] = {};
-    for (int j = 0; j <= ad.k; ++j)
-      for (int i = 0; i <= ad.k; ++i) {
-        double acc = 0.0;
-        for (int t = 0; t <= ad.k; ++t) acc += R[j][t] * ad.R[t][i];
-        P[j][i] = acc;
-      }
-    std::memcpy(ad.R, P, sizeof(P));
-  } else {
-    std::memcpy(ad.R, R, sizeof(R));
-  }
-  ad.pend_transform = true;
-  ad.pend_tk = ad.k;
-  ad.h = h_new;
-  ad.nconst = 0;
-}
-
-// One nonlinear evaluation n(src) into the n buffer (eager launches: replaying
-// the chain from a captured graph per sweep was measured slower at N = 100, the
-// graph launch costing the host more than the launches it replaces).
-nse_status ndf_eval(nse_ctx* c, const double2* src) {
+// One nonlinear evaluation n(src) into the n buffer. `gate`: the device flag
+// of a device-controlled run (null: unconditional).
+nse_status ndf_eval(nse_ctx* c, const double2* src, const int* gate = nullptr) {
   SynthInput in{};
   in.nsrc = 1;
   in.src[0] = src;
@@ -823,171 +778,230 @@ nse_status ndf_eval(nse_ctx* c, const double2* src) {
   out.mode = ANAL_NONLINEAR;
   out.n_out = ndf_buf(c, 5);
   out.state_count = c->state_count;
-  c->ad.stats.evaluations++;
-  return enqueue_chain(c, in, out);
+  return enqueue_chain(c, in, out, gate);
 }
 
-nse_status ndf_correct(nse_ctx* c, int mode, int sweep, double h, const double2* dprev,
-                       double2* dout) {
-  auto& ad = c->ad;
+// Corrector sweep `sweep` (0-based) or the NDF_RHS evaluation. Host-controlled:
+// h, k and the forcing scale from the host state, the last launch publishing the
+// norms; device-controlled (ctl): those from the control block, gated by the
+// sweep slot (k_ndf_decide then runs the controller).
+nse_status ndf_correct(nse_ctx* c, int mode, int sweep, const double2* dprev, double2* dout,
+                       NdfCtl* ctl = nullptr) {
+  const NdfCtl& k = c->ad.c;
   NdfArgs a = ndf_args(c);
   a.mode = mode;
-  a.k = ad.k;
+  a.k = k.k;
   a.n = ndf_buf(c, 5);
-  a.f = ad.forcing;
-  a.fscale = ad.fscale;
-  a.y0 = ndf_buf(c, 0);
-  a.psi = ndf_buf(c, 1);
+  a.f = c->ad.forcing;
+  a.fscale = k.fscale;
   a.dprev = dprev;
   a.dout = dout;
   a.yout = ndf_buf(c, 2);
-  a.h = h;
-  a.ak = ndf_alpha(ad.k);
-  a.nrow = c->d_norms + 4 * sweep;
+  a.h = mode == NDF_RHS ? 0.0 : k.h;
+  a.ak = ndf_alpha(k.k);
+  a.nrow = ctl ? c->d_spread + (int64_t)sweep * kNdfSpreadRow : c->d_norms + 4 * sweep;
   a.sweep = sweep;
-  a.done = reinterpret_cast<unsigned int*>(c->d_norms + 4 * kMaxNewton);
   a.pub = c->d_pub;
-  a.seq = ++c->pub_seq;
+  a.ctl = ctl;
+  a.dsel[0] = ndf_buf(c, 3);
+  a.dsel[1] = ndf_buf(c, 4);
+  if (!ctl) a.seq = ++c->pub_seq;
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
-    a.publish = gi + 1 == c->groups.size();  // stream order: the last launch ends the sweep
+    // stream order: the last launch ends the sweep
+    a.publish = !ctl && gi + 1 == c->groups.size();
     NSE_HIP(c, launch_ndf_correct(c->groups[gi].view(), a, c->stream));
   }
   return NSE_OK;
 }
 
-void ndf_record(nse_ctx* c, double t, double h, double err, int k, int sweeps, int outcome) {
-  nse_adaptive_record r{};
-  r.t = t;
-  r.h = h;
-  r.err = err;
-  r.order = k;
-  r.sweeps = sweeps;
-  r.outcome = outcome;
-  c->ad.log.push_back(r);
+// The corrector can ride in the analysis epilogue (ANAL_NDF) when the context is
+// one group whose analysis is k_analysis_otf.
+bool ndf_fusable(const nse_ctx* c) {
+  if (c->groups.size() != 1) return false;
+  const Group& g = c->groups[0];
+  return g.precision != NSE_PREC_BF16X3 && !(g.precision == NSE_PREC_FP64 && g.mb_anal >= 2);
 }
 
-double ratio_of(double e, double cst, int q, double rtol) {
-  return 1.0 / std::max(0.1, cst * std::pow(e / rtol, 1.0 / (q + 1)));
+// Sweep `sweep` (0-based) of a device-controlled attempt with the corrector in
+// the analysis epilogue.
+nse_status ndf_sweep_fused(nse_ctx* c, int sweep) {
+  const double2* src = sweep == 0 ? ndf_buf(c, 0) : ndf_buf(c, 2);
+  SynthInput in{};
+  in.nsrc = 1;
+  in.src[0] = src;
+  in.coef[0] = 1.0;
+  in.coriolis = 2.0 * c->params.omega * std::sqrt(4.0 * kPi / 3.0);
+  AnalOutput out{};
+  out.mode = ANAL_NDF;
+  out.state_count = c->state_count;
+  out.forcing = c->ad.forcing;
+  out.ctl = c->d_ctl;
+  out.D = c->d_ndf;
+  out.y0 = ndf_buf(c, 0);
+  out.psi = ndf_buf(c, 1);
+  out.dprev = sweep == 0 ? nullptr : ndf_buf(c, 3 + ((sweep - 1) & 1));
+  out.dout = ndf_buf(c, 3 + (sweep & 1));
+  out.yout = ndf_buf(c, 2);
+  out.nrow = c->d_spread + (int64_t)sweep * kNdfSpreadRow;
+  out.kmax = c->ad.p.max_order;
+  const double r = c->ad.p.atol / c->ad.p.rtol;
+  out.thr2 = r * r;
+  return enqueue_chain(c, in, out, &c->d_ctl->gates[sweep]);
 }
 
-// One attempt at (t, h, k). Returns NSE_OK with *done_step = true on
-// acceptance.
-nse_status ndf_attempt(nse_ctx* c, bool last, double t_end, int* nfail) {
+nse_status ndf_failure(nse_ctx* c, int code) {
+  c->ad.active = false;
+  switch (code) {
+    case NDF_FAIL_CORRECTOR: return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
+    case NDF_FAIL_ESTIMATE: return fail(c, NSE_ERR_NONFINITE, "non-finite error estimate");
+    default: return fail(c, NSE_ERR_STATE, "step size underflow at t = %.17g", c->ad.c.t);
+  }
+}
+
+// One attempt with the controller on the host (a forcing callback per time
+// level): a wait for the norms after every sweep from the second on.
+nse_status ndf_attempt_host(nse_ctx* c) {
   auto& ad = c->ad;
-  const int k = ad.k, K = ad.p.max_newton;
-  const double h = ad.h, t = ad.t, rtol = ad.p.rtol;
-  ad.fscale = ad.fn ? ad.fn(ad.user, t + h) : 1.0;
-  nse_status s = ndf_prepare(c, true);
+  NdfCtl& k = ad.c;
+  k.fscale = ad.fn ? ad.fn(ad.user, k.t + k.h) : 1.0;
+  ndf_take_prepare(k, 1);
+  nse_status s = ndf_prepare_host(c);
   if (s != NSE_OK) return s;
+  const int K = k.K;
   double nrm[kMaxNewton][4];
-  double2* dbuf[2] = {ndf_buf(c, 3), ndf_buf(c, 4)};
-  const double2* dprev = nullptr;
-  double2* dcur = nullptr;
-  bool converged = false;
-  int sweeps = 0;
-  double dd_prev = 0.0;
   for (int i = 1; i <= K; ++i) {
-    sweeps = i;
     s = ndf_eval(c, i == 1 ? ndf_buf(c, 0) : ndf_buf(c, 2));
     if (s != NSE_OK) return s;
-    dcur = dbuf[(i - 1) & 1];
-    s = ndf_correct(c, NDF_SWEEP, i - 1, h, dprev, dcur);
+    s = ndf_correct(c, NDF_SWEEP, i - 1, i == 1 ? nullptr : ndf_buf(c, 3 + ((i - 2) & 1)),
+                    ndf_buf(c, 3 + ((i - 1) & 1)));
     if (s != NSE_OK) return s;
-    dprev = dcur;
-    if (K == 1) {
-      s = read_norms(c, 1, nrm);
-      if (s != NSE_OK) return s;
-      if (!std::isfinite(nrm[0][0])) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
-      converged = true;
-      break;
-    }
-    if (i == 1) continue;
+    if (K > 1 && i == 1) continue;  // sweep 1's norms are read with sweep 2's
     s = read_norms(c, i, nrm);
     if (s != NSE_OK) return s;
-    if (i == 2) {
-      dd_prev = nrm[0][0];
-      if (!std::isfinite(dd_prev)) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
+    if (K > 1 && i == 2) {
+      const int r0 = ndf_after_sweep(k, nrm[0]);
+      if (r0 < 0) return ndf_failure(c, -r0);
     }
-    const double dd = nrm[i - 1][0];
-    if (!std::isfinite(dd)) return fail(c, NSE_ERR_NONFINITE, "non-finite corrector");
-    if (dd == 0.0) {
-      converged = true;
+    const int r = ndf_after_sweep(k, nrm[i - 1]);
+    if (r < 0) return ndf_failure(c, -r);
+    if (r == NDF_ENDED) {
+      ad.log.push_back(k.rec);
+      return NSE_OK;
+    }
+  }
+  return fail(c, NSE_ERR_STATE, "attempt did not end after %d sweeps", K);
+}
+
+// Captures kAttemptsPerGraph attempts of the device-controlled run: each is the
+// prepare (run while an attempt is open) and max_newton sweep slots (chain with
+// the corrector, then k_ndf_decide), each slot's kernels gated by its gate.
+nse_status capture_attempt_graph(nse_ctx* c) {
+  if (!c->cap_stream) NSE_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user_stream = c->stream;
+  c->stream = c->cap_stream;
+  struct Restore {
+    nse_ctx* c;
+    hipStream_t s;
+    ~Restore() { c->stream = s; }
+  } restore{c, user_stream};
+  NSE_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  nse_status s = NSE_OK;
+  const int K = c->ad.c.K;
+  const bool fused = ndf_fusable(c);
+  for (int at = 0; at < kAttemptsPerGraph && s == NSE_OK; ++at) {
+    NdfArgs a = ndf_args(c);
+    a.ctl = c->d_ctl;
+    a.dsel[0] = ndf_buf(c, 3);
+    a.dsel[1] = ndf_buf(c, 4);
+    a.spread = c->d_spread;
+    a.spread_words = (int64_t)K * kNdfSpreadRow;
+    hipError_t e = launch_ndf_prepare(a, c->stream);
+    if (e != hipSuccess) {
+      s = hip_fail(c, e, "launch_ndf_prepare");
       break;
     }
-    const double rho = dd_prev > 0.0 ? dd / dd_prev : INFINITY;
-    if (rho >= 0.9) break;
-    if (rho / (1.0 - rho) * dd <= 0.1 * rtol) {
-      converged = true;
-      break;
-    }
-    dd_prev = dd;
-  }
-  if (!converged) {
-    ad.stats.newton_failures++;
-    ndf_record(c, t, h, NAN, k, sweeps, NSE_ATTEMPT_NEWTON_FAIL);
-    ndf_rescale(c, 0.3 * h);
-    return NSE_OK;
-  }
-  const double* row = nrm[sweeps - 1];
-  if (!std::isfinite(row[1]) || !std::isfinite(row[2]) || !std::isfinite(row[3]))
-    return fail(c, NSE_ERR_NONFINITE, "non-finite error estimate");
-  const double err = ndf_error_constant(k) * row[1];
-  if (err > rtol) {
-    ad.stats.error_failures++;
-    ndf_record(c, t, h, err, k, sweeps, NSE_ATTEMPT_ERROR_FAIL);
-    ++*nfail;
-    double ratio;
-    if (*nfail == 1) {
-      ratio = std::max(0.1, 0.833 * std::pow(rtol / err, 1.0 / (k + 1)));
-      if (k > 1) {
-        const double ekm1 = ndf_error_constant(k - 1) * row[2];
-        const double rkm1 =
-            ekm1 > 0.0 ? std::min(1.0, std::max(0.1, 0.769 * std::pow(rtol / ekm1, 1.0 / k)))
-                       : 1.0;
-        if (rkm1 > ratio) {
-          ratio = rkm1;
-          ad.k = k - 1;
-        }
+    for (int i = 1; i <= K && s == NSE_OK; ++i) {
+      if (fused) {
+        s = ndf_sweep_fused(c, i - 1);
+      } else {
+        s = ndf_eval(c, i == 1 ? ndf_buf(c, 0) : ndf_buf(c, 2), &c->d_ctl->gates[i - 1]);
+        if (s == NSE_OK)
+          s = ndf_correct(c, NDF_SWEEP, i - 1, i == 1 ? nullptr : ndf_buf(c, 3 + ((i - 2) & 1)),
+                          ndf_buf(c, 3 + ((i - 1) & 1)), c->d_ctl);
       }
-    } else {
-      ratio = 0.5;
-      if (*nfail >= 3) ad.k = 1;
-    }
-    ndf_rescale(c, ratio * h);
-    return NSE_OK;
-  }
-  // accepted
-  ndf_record(c, t, h, err, k, sweeps, NSE_ATTEMPT_ACCEPTED);
-  ad.stats.accepted++;
-  *nfail = 0;
-  ad.pend_accept = true;
-  ad.pend_k = k;
-  ad.pend_d = dcur;
-  ad.t = last ? t_end : t + h;
-  ad.nconst++;
-  if (ad.nconst >= k + 2) {
-    double r = ratio_of(err, 1.2, k, rtol);
-    int knew = k;
-    if (k > 1) {
-      const double rm = ratio_of(ndf_error_constant(k - 1) * row[2], 1.3, k - 1, rtol);
-      if (rm > r) {
-        r = rm;
-        knew = k - 1;
-      }
-    }
-    if (k < ad.p.max_order) {
-      const double rp = ratio_of(ndf_error_constant(k + 1) * row[3], 1.4, k + 1, rtol);
-      if (rp > r) {
-        r = rp;
-        knew = k + 1;
-      }
-    }
-    if (r > 1.0) {
-      ad.k = knew;
-      ndf_rescale(c, std::min(r * h, ad.p.hmax > 0.0 ? ad.p.hmax : INFINITY));
+      if (s != NSE_OK) break;
+      e = launch_ndf_decide(c->d_ctl, c->d_spread + (int64_t)(i - 1) * kNdfSpreadRow, i - 1,
+                            c->d_log, c->ad.sched, c->stream);
+      if (e != hipSuccess) s = hip_fail(c, e, "launch_ndf_decide");
     }
   }
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+  if (s != NSE_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    return hip_fail(c, ei, "hipGraphInstantiate");
+  }
+  c->ad_graph = gr;
+  c->ad_exec = ex;
   return NSE_OK;
+}
+
+// Advances with the controller on the device: the host state goes to the
+// device, batches of captured attempt sequences run (the attempts after the
+// end do nothing), and the state and the new attempt records come back after
+// each batch.
+nse_status advance_device(nse_ctx* c) {
+  auto& ad = c->ad;
+  NdfCtl& k = ad.c;
+  if (!c->ad_exec) {
+    nse_status s = capture_attempt_graph(c);
+    if (s != NSE_OK) return s;
+  }
+  ndf_open_attempt(k, ad.sched);  // the first attempt; the device opens the others
+  if (k.status) return ndf_failure(c, k.status);
+  if (k.done) return NSE_OK;
+  *c->h_ctl = k;
+  NSE_HIP(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(NdfCtl), hipMemcpyHostToDevice, c->stream));
+  long long read = k.nlog;
+  std::vector<nse_adaptive_record> recs;
+  for (;;) {
+    // enough attempts for the remaining interval at the current step, plus a
+    // margin for rejections; the surplus ones find the gate closed
+    const double need = (k.t_end - k.t) / k.h * 1.1 + 2.0;
+    int graphs = (int)std::min<double>(kMaxGraphsPerBatch, std::ceil(need / kAttemptsPerGraph));
+    graphs = std::max(graphs, 1);
+    for (int i = 0; i < graphs; ++i) NSE_HIP(c, hipGraphLaunch(c->ad_exec, c->stream));
+    NSE_HIP(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(NdfCtl), hipMemcpyDeviceToHost,
+                              c->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    NSE_HIP(c, hipStreamSynchronize(c->stream));
+    ad.waits++;
+    ad.wait_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    k = *c->h_ctl;
+    const long long fresh = k.nlog - read;
+    if (fresh > kNdfLogCap) return fail(c, NSE_ERR_STATE, "attempt log overflow");
+    if (fresh > 0) {
+      recs.resize((size_t)fresh);
+      const long long first = read % kNdfLogCap;
+      const long long n1 = std::min<long long>(fresh, kNdfLogCap - first);
+      NSE_HIP(c, hipMemcpy(recs.data(), c->d_log + first, sizeof(nse_adaptive_record) * n1,
+                           hipMemcpyDeviceToHost));
+      if (fresh > n1)
+        NSE_HIP(c, hipMemcpy(recs.data() + n1, c->d_log,
+                             sizeof(nse_adaptive_record) * (fresh - n1), hipMemcpyDeviceToHost));
+      ad.log.insert(ad.log.end(), recs.begin(), recs.end());
+      read = k.nlog;
+    }
+    if (k.status) return ndf_failure(c, k.status);
+    if (k.done) return NSE_OK;
+  }
 }
 
 }  // namespace
@@ -1210,6 +1224,12 @@ nse_status nse_sphere_destroy(nse_ctx* ctx) {
   (void)hipFree(ctx->d_diag);
   (void)hipFree(ctx->d_norms);
   if (ctx->h_pub) (void)hipHostFree(ctx->h_pub);
+  drop_attempt_graph(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  (void)hipFree(ctx->d_ctl);
+  (void)hipFree(ctx->d_log);
+  (void)hipFree(ctx->d_spread);
+  if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
   delete ctx;
   return NSE_OK;
 }
@@ -1596,9 +1616,10 @@ nse_status nse_inertial_manifold(nse_ctx* ctx, const double* alpha_src, int32_t 
   return NSE_OK;
 }
 
-nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
-                              const nse_adaptive_params* params, const double* forcing,
-                              nse_forcing_fn fn, void* user) {
+static nse_status adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
+                                 const nse_adaptive_params* params, const double* forcing,
+                                 nse_forcing_fn fn, void* user,
+                                 const nse_forcing_schedule* sched) {
   if (!ctx) return NSE_ERR_ARG;
   if (!alpha0 || !params) return fail(ctx, NSE_ERR_ARG, "alpha0 and params must be non-NULL");
   const nse_adaptive_params& p = *params;
@@ -1611,26 +1632,47 @@ nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
   if (p.max_newton < 1 || p.max_newton > kMaxNewton)
     return fail(ctx, NSE_ERR_ARG, "max_newton must be 1..8");
   if (!std::isfinite(t0)) return fail(ctx, NSE_ERR_ARG, "t0 must be finite");
+  if (sched) {
+    const nse_forcing_schedule& f = *sched;
+    if (!std::isfinite(f.t_on) || !std::isfinite(f.before) || !std::isfinite(f.amp) ||
+        !std::isfinite(f.omega) || !std::isfinite(f.phase) || !std::isfinite(f.decay))
+      return fail(ctx, NSE_ERR_ARG, "forcing schedule entries must be finite");
+  }
   auto& ad = ctx->ad;
   ad = nse_ctx::Adaptive{};
   ad.p = p;
   ad.forcing = (const double2*)forcing;
   ad.fn = fn;
   ad.user = user;
-  ad.t = t0;
+  if (sched) {
+    ad.sched = *sched;
+  } else {
+    ad.sched.t_on = INFINITY;  // s = 1
+    ad.sched.before = 1.0;
+  }
+  NdfCtl& k = ad.c;
+  k.rtol = p.rtol;
+  k.hmax = p.hmax > 0.0 ? p.hmax : INFINITY;
+  k.kmax = p.max_order;
+  k.K = p.max_newton;
+  k.t = t0;
+  k.k = 1;
+  drop_attempt_graph(ctx);  // its arguments name this run's forcing and schedule
   nse_status s = ensure_ndf_buffers(ctx, p.max_order + 3);
   if (s != NSE_OK) return s;
   const size_t bytes = sizeof(double2) * (size_t)ctx->state_count;
   NSE_HIP(ctx, hipMemcpyAsync(ctx->d_ndf, alpha0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   NSE_HIP(ctx, hipMemsetAsync(ctx->d_ndf + ctx->state_count, 0, bytes * (ctx->ndf_depth - 1),
                               ctx->stream));
-  ad.fscale = fn ? fn(user, t0) : 1.0;
-  s = ndf_prepare(ctx, false);  // clears the norms
+  k.fscale = fn ? fn(user, t0) : schedule_scale(ad.sched, t0);
+  ndf_take_prepare(k, 0);  // nothing pending: clears the norms
+  s = ndf_prepare_host(ctx);
   if (s != NSE_OK) return s;
   s = ndf_eval(ctx, ctx->d_ndf);
   if (s != NSE_OK) return s;
-  s = ndf_correct(ctx, NDF_RHS, 0, 0.0, nullptr, ctx->d_ndf + ctx->state_count);
+  s = ndf_correct(ctx, NDF_RHS, 0, nullptr, ctx->d_ndf + ctx->state_count);
   if (s != NSE_OK) return s;
+  k.evaluations = 1;
   double nrm[kMaxNewton][4];
   s = read_norms(ctx, 1, nrm);
   if (s != NSE_OK) return s;
@@ -1640,62 +1682,89 @@ nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
   return NSE_OK;
 }
 
+nse_status nse_adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
+                              const nse_adaptive_params* params, const double* forcing,
+                              nse_forcing_fn fn, void* user) {
+  return adaptive_begin(ctx, alpha0, t0, params, forcing, fn, user, nullptr);
+}
+
+nse_status nse_adaptive_begin_scheduled(nse_ctx* ctx, const double* alpha0, double t0,
+                                        const nse_adaptive_params* params,
+                                        const double* forcing,
+                                        const nse_forcing_schedule* schedule) {
+  return adaptive_begin(ctx, alpha0, t0, params, forcing, nullptr, nullptr, schedule);
+}
+
 nse_status nse_adaptive_advance(nse_ctx* ctx, double t_end, double* alpha_out,
                                 nse_adaptive_stats* stats) {
   if (!ctx) return NSE_ERR_ARG;
   auto& ad = ctx->ad;
+  NdfCtl& k = ad.c;
   if (!ad.active) return fail(ctx, NSE_ERR_STATE, "nse_adaptive_begin has not been called");
-  if (!(t_end >= ad.t) || !std::isfinite(t_end))
+  if (!(t_end >= k.t) || !std::isfinite(t_end))
     return fail(ctx, NSE_ERR_ARG, "t_end must be finite and >= the current time");
   const double rtol = ad.p.rtol;
-  const double hmax = ad.p.hmax > 0.0 ? ad.p.hmax : INFINITY;
-  nse_status s = NSE_OK;
-  if (t_end > ad.t && !ad.started) {
-    double h = std::min(hmax, t_end - ad.t);
+  if (t_end > k.t && !ad.started) {
+    double h = std::min(k.hmax, t_end - k.t);
     if (ad.p.h0 > 0.0)
       h = std::min(h, ad.p.h0);
     else if (ad.fnorm > 0.0 && h * ad.fnorm / (0.8 * std::sqrt(rtol)) > 1.0)
       h = 0.8 * std::sqrt(rtol) / ad.fnorm;
     // D[1] holds F(t0, alpha0): scale it to h F
-    ad.pend_transform = true;
-    ad.pend_tk = 1;
-    std::memset(ad.R, 0, sizeof(ad.R));
-    ad.R[0][0] = 1.0;
-    ad.R[1][1] = h;
-    ad.h = h;
-    ad.k = 1;
+    k.pend_transform = 1;
+    k.pend_tk = 1;
+    for (int j = 0; j <= kNdfMaxOrder; ++j)
+      for (int i = 0; i <= kNdfMaxOrder; ++i) k.R[j][i] = 0.0;
+    k.R[0][0] = 1.0;
+    k.R[1][1] = h;
+    k.h = h;
+    k.k = 1;
     ad.started = true;
   }
-  int nfail = 0;
-  while (ad.t < t_end) {
-    double h_new = std::min(ad.h, hmax);
-    bool last = false;
-    if (ad.t + 1.1 * h_new >= t_end) {
-      h_new = t_end - ad.t;
-      last = true;
-    }
-    if (h_new != ad.h) ndf_rescale(ctx, h_new);
-    if (ad.h <= 16.0 * 2.220446049250313e-16 * std::fabs(ad.t)) {
-      ad.active = false;
-      return fail(ctx, NSE_ERR_STATE, "step size underflow at t = %.17g", ad.t);
-    }
-    s = ndf_attempt(ctx, last, t_end, &nfail);
+  k.t_end = t_end;
+  k.done = 0;
+  nse_status s = NSE_OK;
+  if (!(k.t < t_end)) {
+    // nothing to integrate
+  } else if (!ad.fn && !ctx->profiling) {
+    s = advance_device(ctx);
     if (s != NSE_OK) {
       ad.active = false;
       return s;
     }
+  } else {
+    for (;;) {
+      const int r = ndf_begin_attempt(k);
+      if (r == NDF_STOP) break;
+      if (r < 0) return ndf_failure(ctx, -r);
+      s = ndf_attempt_host(ctx);
+      if (s != NSE_OK) {
+        ad.active = false;
+        return s;
+      }
+    }
   }
-  if (ad.pend_accept || ad.pend_transform) {
-    s = ndf_prepare(ctx, false);
+  if (k.pend_accept || k.pend_transform) {
+    ndf_take_prepare(k, 0);
+    s = ndf_prepare_host(ctx);
     if (s != NSE_OK) return s;
   }
   if (alpha_out)
     NSE_HIP(ctx, hipMemcpyAsync(alpha_out, ctx->d_ndf, sizeof(double2) * ctx->state_count,
                                 hipMemcpyDeviceToDevice, ctx->stream));
-  ad.stats.t = ad.t;
-  ad.stats.h = ad.h;
-  ad.stats.order = ad.k;
-  if (stats) *stats = ad.stats;
+  if (stats) {
+    nse_adaptive_stats st{};
+    st.t = k.t;
+    st.h = k.h;
+    st.order = k.k;
+    st.accepted = k.accepted;
+    st.error_failures = k.error_failures;
+    st.newton_failures = k.newton_failures;
+    st.evaluations = k.evaluations;
+    st.waits = ad.waits;
+    st.wait_seconds = ad.wait_seconds;
+    *stats = st;
+  }
   return NSE_OK;
 }
 

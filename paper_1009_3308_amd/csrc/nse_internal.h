@@ -90,7 +90,14 @@ struct GroupView {
   const double2* tw;        // [M] exp(-2 pi i k / M)
   const int64_t* off;       // [nb] complex-slot offset of each member in a state
   const double* nu;         // [nb]
+  const int* gate;          // null, or a device flag: the chain kernels do nothing while it is 0
 };
+
+// True when the launch belongs to a gated sequence whose flag is closed (read
+// once per workgroup; uniform, so the whole workgroup returns).
+__device__ inline bool gate_closed(const GroupView& g) {
+  return g.gate && __hip_atomic_load(g.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
 
 struct FftPlan {
   int nstages;
@@ -115,7 +122,9 @@ struct SynthInput {
 // SYNTH_ADJ: the four forward fields plus a fifth, lambda^(-1/2) n_bar (the
 // adjoint of the analysis), written to GroupView::Fa.
 enum SynthMode { SYNTH_NONLINEAR = 0, SYNTH_GRID = 1, SYNTH_ADJ = 2 };
-enum AnalMode { ANAL_NONLINEAR = 0, ANAL_STEP_ITER = 1, ANAL_STEP_FINAL = 2 };
+enum AnalMode { ANAL_NONLINEAR = 0, ANAL_STEP_ITER = 1, ANAL_STEP_FINAL = 2, ANAL_NDF = 3 };
+
+struct NdfCtl;  // ndf_control.h
 
 struct AnalOutput {
   int mode;
@@ -129,6 +138,17 @@ struct AnalOutput {
   const double2* forcing;    // may be null
   double2* iter;             // ANAL_STEP_ITER output
   int* nonfinite;            // may be null
+  // ANAL_NDF (k_analysis_otf): the corrector sweep of a device-controlled
+  // adaptive run in the epilogue, with h, the order and the forcing scale from
+  // the control block: d = (h (s f - n) - h nu lambda y0 - psi) / (alpha_k + h nu lambda),
+  // y = y0 + d, and the sweep's four weighted max norms (as k_ndf_correct)
+  const NdfCtl* ctl;
+  const double2* D;          // [kmax + 3][state_count] backward differences
+  const double2 *y0, *psi, *dprev;  // dprev null on the first sweep
+  double2 *dout, *yout;
+  unsigned long long* nrow;  // the sweep's spread norm row (squares, IEEE bits, atomic max)
+  int kmax;
+  double thr2;               // (atol / rtol)^2
 };
 
 // Adaptive NDF integrator (Section 4.2, eq. (ode_disc) in backward differences
@@ -171,6 +191,14 @@ struct NdfArgs {
   unsigned int* done;          // [max sweeps] workgroup counters, zeroed by k_ndf_prepare
   unsigned long long* pub;     // host-mapped: [4 x max sweeps] norms, then the sequence word
   unsigned long long seq;
+  // device-controlled integration: the attempt's parameters come from the
+  // control block (k_ndf_prepare: its prepare snapshot, run while an attempt is
+  // open; k_ndf_correct: h, k and the forcing scale, run while the gate of
+  // sweep slot `sweep` is open)
+  const NdfCtl* ctl;
+  double2* dsel[2];            // the two correction buffers (accepted one chosen by the control block)
+  unsigned long long* spread;  // the sweeps' spread norm rows (nrow points into it), zeroed
+  int64_t spread_words;        // by k_ndf_prepare
 };
 
 // Launchers (each enqueues on `s` and returns the launch status).

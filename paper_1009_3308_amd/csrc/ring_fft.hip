@@ -527,6 +527,7 @@ __device__ __forceinline__ void wave_fft(double2* x, const double2* tw, int lane
 // fused pass, waves 0..2 the forward transforms.
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int M = 3 * S, PS = wave_row(S);
   const int N = g.N, nlat = g.nlat;
   const int lat = xcd_item(blockIdx.x, 8);
@@ -640,6 +641,7 @@ size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(
 template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode,
                                              double* grid_out) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int PTS = (MAXM + NT - 1) / NT;
   const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
   const int lat = xcd_item(blockIdx.x, 8);

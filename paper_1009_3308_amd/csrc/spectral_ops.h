@@ -3,6 +3,7 @@
 // the per-degree epilogue of the analysis (post-scaling and time step).
 #pragma once
 
+#include "ndf_control.h"
 #include "nse_internal.h"
 
 namespace nse {
@@ -118,10 +119,25 @@ __device__ inline void build_panel(double2* pan, const double2* a, int N, int m,
 // forcing) and in[1 + j] = hist[j][l,m] for j < depth; nothing in the nonlinear
 // mode. Kernels can request them early and keep them until finish_degree_from.
 constexpr int kDegreeInputs = kMaxStepCoef;  // forcing + up to kMaxStepCoef - 1 history slots
+// ANAL_NDF: in[0] = f, in[1] = D[0], in[2] = y0, in[3] = psi, in[4] = dprev,
+// in[5] = D[order] (order > 1), in[6] = D[order + 1] (order < kmax).
 __device__ inline void load_degree_inputs(const GroupView& g, const AnalOutput& out, int b, int m,
                                           int k, double2* in) {
   if (out.mode == ANAL_NONLINEAR) return;
   const int64_t slot = g.off[b] + coeff_offset(g.N, m) + k;
+  if (out.mode == ANAL_NDF) {
+    const double2 z = make_double2(0.0, 0.0);
+    const int64_t S = out.state_count;
+    const int q = out.ctl->k;
+    in[0] = out.forcing ? out.forcing[slot] : z;
+    in[1] = out.D[slot];
+    in[2] = out.y0[slot];
+    in[3] = out.psi[slot];
+    in[4] = out.dprev ? out.dprev[slot] : z;
+    in[5] = q > 1 ? out.D[(int64_t)q * S + slot] : z;
+    in[6] = q < out.kmax ? out.D[(int64_t)(q + 1) * S + slot] : z;
+    return;
+  }
   in[0] = out.forcing ? out.forcing[slot] : make_double2(0.0, 0.0);
 #pragma unroll
   for (int j = 0; j < kMaxStepCoef - 1; ++j)
@@ -129,8 +145,10 @@ __device__ inline void load_degree_inputs(const GroupView& g, const AnalOutput& 
                                 : make_double2(0.0, 0.0);
 }
 
+template <bool NDF = false>
 __device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& out, int b, int m,
-                                          int k, double sx, double sy, const double2* in);
+                                          int k, double sx, double sy, const double2* in,
+                                          double* nv = nullptr);
 
 __device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, int b, int m,
                                      int k, double sx, double sy) {
@@ -140,8 +158,12 @@ __device__ inline void finish_degree(const GroupView& g, const AnalOutput& out, 
 }
 
 // As finish_degree, with the step-update inputs already loaded (load_degree_inputs).
+// NDF (out.mode == ANAL_NDF): nv receives the coefficient's four weighted norm
+// terms (squares).
+template <bool NDF>
 __device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& out, int b, int m,
-                                          int k, double sx, double sy, const double2* in) {
+                                          int k, double sx, double sy, const double2* in,
+                                          double* nv) {
   const int l = m + k;
   const double lam = (double)l * (l + 1);
   double2 n = make_double2(0.0, 0.0);
@@ -152,6 +174,33 @@ __device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& 
   const int64_t slot = g.off[b] + coeff_offset(g.N, m) + k;
   if (out.mode == ANAL_NONLINEAR) {
     out.n_out[slot] = n;
+    return;
+  }
+  if constexpr (NDF) {
+    // the corrector of k_ndf_correct, with n in registers
+    const NdfCtl& c = *out.ctl;
+    const int q = c.k;
+    const double h = c.h, fs = c.fscale;
+    const double Lam = g.nu[b] * lam;
+    const double2 f = make_double2(fs * in[0].x, fs * in[0].y);
+    const double2 D0 = in[1], y0 = in[2], ps = in[3], dp = in[4];
+    const double hL = h * Lam;
+    const double den = ndf_alpha(q) + hL;
+    double2 d = make_double2((h * (f.x - n.x) - hL * y0.x - ps.x) / den,
+                             (h * (f.y - n.y) - hL * y0.y - ps.y) / den);
+    if (l == 0) d = make_double2(0.0, 0.0);
+    if (m == 0) d.y = 0.0;
+    const double2 y = make_double2(y0.x + d.x, y0.y + d.y);
+    out.dout[slot] = d;
+    out.yout[slot] = y;
+    const double wt2 = fmax(fmax(D0.x * D0.x + D0.y * D0.y, y.x * y.x + y.y * y.y), out.thr2);
+    const double2 e0 = make_double2(d.x - dp.x, d.y - dp.y);
+    nv[0] = (e0.x * e0.x + e0.y * e0.y) / wt2;
+    nv[1] = (d.x * d.x + d.y * d.y) / wt2;
+    const double2 e2 = make_double2(in[5].x + d.x, in[5].y + d.y);
+    const double2 e3 = make_double2(d.x - in[6].x, d.y - in[6].y);
+    nv[2] = q > 1 ? (e2.x * e2.x + e2.y * e2.y) / wt2 : 0.0;
+    nv[3] = q < out.kmax ? (e3.x * e3.x + e3.y * e3.y) / wt2 : 0.0;
     return;
   }
   const double2 f = in[0];

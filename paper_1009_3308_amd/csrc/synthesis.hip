@@ -64,6 +64,7 @@ size_t synthesis_lds_bytes(int N, int NF) {
 template <typename TT, int NF, int R = 1>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthInput in,
                                                               int mode) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int kRed = 4 * NF;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 // latitudes per lane (R) and the cross-wave sums are those of k_synthesis.
 template <int R>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
+  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int kRed = 16;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;

@@ -1,7 +1,8 @@
 """Adaptive NDF integration on the GPU against the oracle's integrator.
 
 The GPU controller takes the same decisions as the oracle's (orders 1..5 of eq.
-(ode_disc), step and order control at a relative tolerance): the attempt logs
+(ode_disc), step and order control at a relative tolerance), whether it runs on
+the host (forcing callbacks) or on the device (no callback): the attempt logs
 must agree in order, outcome and corrector sweeps exactly, in t and h to 1e-9
 relative, and the states to 1e-10 of their largest coefficient (the nonlinear
 terms agree to ~1e-14 per evaluation; the step-size feedback amplifies that by a
@@ -39,14 +40,19 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-def _compare_logs(glog, olog, label):
+def _compare_logs(glog, olog, label, stops=()):
+    """Attempt logs: order, sweeps and outcome exactly, t to 1e-9 (absolute below
+    1), h to 1e-9 relative, except for a step shortened or stretched to end at a
+    stop, whose h = stop - t carries the absolute deviation of t."""
     assert len(glog) == len(olog), (label, len(glog), len(olog))
     for i, (g, o) in enumerate(zip(glog, olog)):
         gt, gh, gk, gs, gout, gerr = g
         ot, oh, ok, osw, oout, oerr = o
         assert (gk, gs, gout) == (ok, osw, oout), (label, i, g, o)
-        assert abs(gt - ot) <= 1e-9 * max(1.0, abs(ot)), (label, i, g, o)
-        assert abs(gh - oh) <= 1e-9 * oh, (label, i, g, o)
+        tol_t = 1e-9 * max(1.0, abs(ot))
+        assert abs(gt - ot) <= tol_t, (label, i, g, o)
+        at_stop = any(abs(ot + oh - t) <= 1e-12 * max(1.0, t) for t in stops)
+        assert abs(gh - oh) <= (tol_t if at_stop else 1e-9 * oh), (label, i, g, o)
         if oout != A.NEWTON_FAIL:
             assert abs(gerr - oerr) <= 1e-7 * oerr + 1e-300, (label, i, g, o)
 
@@ -88,7 +94,7 @@ def test_adaptive_matches_oracle(N, nu, T, rtol, max_newton):
                                max_newton=max_newton)
     integ.begin(O.to_tensor(a0), 0.0)
     o = integ.advance(T)
-    _compare_logs(glog, integ.log, f"N={N}")
+    _compare_logs(glog, integ.log, f"N={N}", (T,))
     scale = float(o.abs().max())
     diff = float((g - o).abs().max())
     _say(f"  attempts {len(glog)} accepted {stats['accepted']} evals {stats['evaluations']} "
@@ -96,6 +102,9 @@ def test_adaptive_matches_oracle(N, nu, T, rtol, max_newton):
     assert stats["t"] == T
     assert stats["accepted"] == sum(1 for r in glog if r[4] == A.ACCEPTED)
     assert diff <= 1e-10 * scale
+    # no callback: the controller ran on the device, the host waited once for
+    # F(t0) and once per batch of attempts
+    assert stats["waits"] <= 2 + len(glog) // 4, stats
 
 
 def test_adaptive_stops_and_time_dependent_forcing():
@@ -128,7 +137,43 @@ def test_adaptive_stops_and_time_dependent_forcing():
     for t, g in zip(stops, gouts):
         o = integ.advance(t)
         assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
-    _compare_logs(glog, integ.log, "stops")
+    _compare_logs(glog, integ.log, "stops", stops)
+
+
+def _schedule_scale(sc, t):
+    """s(t) of a forcing schedule, as the header defines it."""
+    if t <= sc.t_on:
+        return sc.before
+    return sc.amp * math.cos(sc.omega * t + sc.phase) * math.exp(-sc.decay * (t - sc.t_on))
+
+
+def test_adaptive_device_schedule_and_stops():
+    # a forcing scale switched on inside the run and evaluated by the device,
+    # several stops (each advance a new batch sequence on the same graph)
+    N, nu = 31, 1e-3
+    _say(f"case adaptive device schedule N={N}")
+    a0 = I.initial_state(N)
+    f0 = I.forcing(N)
+    sc = pkg.ForcingSchedule(t_on=0.6, before=1.0, amp=1.3, omega=7.0, phase=0.4, decay=2.0)
+    s = pkg.Sphere([(N, 0, nu)], omega=OMEGA, dt=1e-3, order=2)
+    s.adaptive_begin(pkg.to_device(a0), 0.25, forcing=(pkg.to_device(f0), sc))
+    stops = (0.5, 0.75, 1.5, 1.5, 2.0)
+    gouts = []
+    for t in stops:
+        out, stats = s.adaptive_advance(t)
+        assert stats["t"] == t
+        gouts.append(out.cpu())
+    glog = s.adaptive_log()
+    s.close()
+    ft = O.to_tensor(f0)
+    integ = _oracle_integrator(N, [nu], lambda t: ft * _schedule_scale(sc, t))
+    integ.begin(O.to_tensor(a0), 0.25)
+    for t, g in zip(stops, gouts):
+        o = integ.advance(t)
+        assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
+    _compare_logs(glog, integ.log, "schedule stops", stops)
+    _say(f"  attempts {len(glog)} waits {stats['waits']}")
+    assert stats["waits"] <= 1 + len(stops) + len(glog) // 4
 
 
 def test_adaptive_members_form_one_system():
@@ -146,7 +191,7 @@ def test_adaptive_members_form_one_system():
     integ = _oracle_integrator(N, nus, lambda t: ft)
     integ.begin(O.to_tensor(a0), 0.0)
     o = integ.advance(1.5)
-    _compare_logs(glog, integ.log, "members")
+    _compare_logs(glog, integ.log, "members", (1.5,))
     assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
 
 
@@ -188,7 +233,7 @@ def test_adaptive_example1_recovers_exact_flow(rtol):
                           atol=rtol * 1e-3, project=lambda y: O.clean(y, N))
     integ.begin(O.to_tensor(I.example1_state(N, N, 0.0, NU)), 0.0)
     o = integ.advance(T)
-    _compare_logs(glog, integ.log, "example1")
+    _compare_logs(glog, integ.log, "example1", (T,))
     assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
 
 
@@ -204,6 +249,10 @@ def test_adaptive_argument_errors():
         with pytest.raises(pkg.NseError) as e:
             s.adaptive_begin(a0, 0.0, **kw)
         assert e.value.status == pkg.NSE_ERR_ARG
+    bad = pkg.ForcingSchedule(t_on=0.0, before=1.0, amp=math.nan, omega=1.0, phase=0.0, decay=0.0)
+    with pytest.raises(pkg.NseError) as e:
+        s.adaptive_begin(a0, 0.0, forcing=(s.new_state(), bad))
+    assert e.value.status == pkg.NSE_ERR_ARG
     s.adaptive_begin(a0, 1.0)
     with pytest.raises(pkg.NseError) as e:
         s.adaptive_advance(0.5)
@@ -229,20 +278,24 @@ def test_adaptive_hmax_and_h0():
     integ = _oracle_integrator(N, [nu], lambda t: ft, h0=1e-3, hmax=0.02)
     integ.begin(O.to_tensor(a0), 0.0)
     o = integ.advance(1.0)
-    _compare_logs(glog, integ.log, "hmax")
+    _compare_logs(glog, integ.log, "hmax", (1.0,))
     assert float((out.cpu() - o).abs().max()) <= 1e-10 * float(o.abs().max())
 
 
-def test_adaptive_example2_matches_oracle():
+@pytest.mark.parametrize("control", ["host", "device"])
+def test_adaptive_example2_matches_oracle(control):
     # the paper's Example 2 setting (N = 100, nu = 1e-4, Omega = 1, random initial
-    # flow of degrees 1..20, forcing f_{3,0}) over a short interval
+    # flow of degrees 1..20, forcing f_{3,0}) over a short interval; its forcing
+    # scale as a host callback (host control) or as a device schedule
     N, nu, omega, T = 100, 1e-4, 1.0, 0.08
-    _say(f"case adaptive example 2 N={N} T={T}")
+    _say(f"case adaptive example 2 N={N} T={T} control={control}")
     a0 = I.example2_state(N, nu)
     s = pkg.Sphere([(N, 0, nu)], omega=omega, dt=1e-3, order=2)
     F = s.new_state()
     F[I.index(N, 3, 0)] = 1.0
-    s.adaptive_begin(pkg.to_device(a0), 0.0, forcing=(F, I.example2_force))
+    scale = (I.example2_force if control == "host"
+             else pkg.ForcingSchedule(**I.example2_schedule()))
+    s.adaptive_begin(pkg.to_device(a0), 0.0, forcing=(F, scale))
     out, stats = s.adaptive_advance(T)
     glog = s.adaptive_log()
     g = out.cpu()
@@ -253,7 +306,7 @@ def test_adaptive_example2_matches_oracle():
     integ.begin(O.to_tensor(a0), 0.0)
     o = integ.advance(T)
     _say(f"  attempts {len(glog)} sweeps {sum(r[3] for r in glog)}")
-    _compare_logs(glog, integ.log, "example2")
+    _compare_logs(glog, integ.log, "example2", (T,))
     assert float((g - o).abs().max()) <= 1e-10 * float(o.abs().max())
 
 
