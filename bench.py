@@ -411,12 +411,12 @@ def example2_timing(pkg, torch, T=60.0, N=100, nu=1e-4, omega=1.0, rtol=1e-3):
         # evaluation cost in fixed graph-replayed steps (one evaluation per step)
         h = s.new_history()
         h[0] = a0
-        s.step(h, F, 0, 20)
+        s.step(h, F, 0, 200)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.step(h, F, 20, 500)
+        s.step(h, F, 200, 2000)
         torch.cuda.synchronize()
-        eval_us = 1e6 * (time.perf_counter() - t0) / 500
+        eval_us = 1e6 * (time.perf_counter() - t0) / 2000
         # the forcing scale of Example 2 as a device schedule: the step and order
         # control runs on the device (a host callback would make the host decide
         # every sweep; that path is timed below over t = 0..T/10)

@@ -2,8 +2,9 @@
 // orders 1..5, written in backward differences at a quasi-constant step).
 // k_ndf_prepare and k_ndf_correct are elementwise over the state; the nonlinear
 // term between them comes from the synthesis / ring / analysis chain. On a
-// device-controlled run k_ndf_decide runs the controller of ndf_control.h
-// after each sweep and opens the next attempt.
+// device-controlled run k_ndf_step opens every sweep slot: the controller of
+// ndf_control.h on the previous sweep's norms and, when an attempt has just
+// been opened, its prepare.
 #include "ndf_control.h"
 
 namespace nse {
@@ -13,76 +14,30 @@ namespace {
 __device__ inline double2 zero2() { return make_double2(0.0, 0.0); }
 __device__ inline double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
 
-// The control block in LDS: copied in by the whole workgroup, worked on by
-// thread 0, copied back.
+// The control block, copied through LDS in 8-byte words.
 constexpr int kCtlWords = sizeof(NdfCtl) / sizeof(unsigned long long);
 static_assert(sizeof(NdfCtl) % sizeof(unsigned long long) == 0, "8-byte words");
 
-__device__ inline void ctl_load(NdfCtl* sc, const NdfCtl* c) {
-  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(c);
-  unsigned long long* dst = reinterpret_cast<unsigned long long*>(sc);
-  for (int i = threadIdx.x; i < kCtlWords; i += blockDim.x) dst[i] = src[i];
-  __syncthreads();
-}
-__device__ inline void ctl_store(NdfCtl* c, const NdfCtl* sc) {
-  __syncthreads();
-  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sc);
-  unsigned long long* dst = reinterpret_cast<unsigned long long*>(c);
-  for (int i = threadIdx.x; i < kCtlWords; i += blockDim.x) dst[i] = src[i];
-}
-
-// Runs the controller after sweep slot `slot` (ndf_decide) if that slot ran:
-// the norms of the sweep, the next slot's gate or the attempt's record (to the
-// log ring) and the opening of the next attempt.
-__global__ __launch_bounds__(64) void k_ndf_decide(NdfCtl* c, const unsigned long long* spread_row,
-                                                   int slot, nse_adaptive_record* log,
-                                                   nse_forcing_schedule sched) {
-  static_assert(kNdfSpread == 64, "one copy per lane");
-  if (__hip_atomic_load(&c->gates[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
-  __shared__ NdfCtl sc;
-  // the sweep's norms: the maximum over the spread copies (lane t: copy t)
-  double v[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    v[q] = __longlong_as_double((long long)spread_row[threadIdx.x * kNdfSpreadStride + q]);
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o, 64));
-  ctl_load(&sc, c);
-  if (threadIdx.x == 0) {
-    double row[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) row[q] = sqrt(v[q]);
-    if (ndf_decide(sc, slot, row, sched) == NDF_ENDED) log[(sc.nlog - 1) % kNdfLogCap] = sc.rec;
-  }
-  ctl_store(c, &sc);
-}
-
 // Accepted-step update of the differences, rescaling to a new step and the
-// predictor of the next attempt, one state slot per thread.
-__global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
-  const NdfCtl* ctl = a.ctl;
-  if (ctl && __hip_atomic_load(&ctl->open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-    return;
-  if (blockIdx.x == 0 && (int)threadIdx.x < a.nnorms) a.norms[threadIdx.x] = 0ull;
-  if (blockIdx.x == 0 && a.done && (int)threadIdx.x < a.nnorms / 4) a.done[threadIdx.x] = 0u;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a.spread)
-    for (int64_t w = s; w < a.spread_words; w += (int64_t)gridDim.x * blockDim.x) a.spread[w] = 0ull;
-  if (s >= a.S) return;
-  const int accept = ctl ? ctl->prep_accept : a.accept;
-  const int transform = ctl ? ctl->prep_transform : a.transform;
-  const int predict = ctl ? ctl->prep_predict : a.predict;
-  const int k = ctl ? ctl->prep_k : a.k;
-  const auto R = ctl ? ctl->prepR : a.R;
+// predictor of the next attempt for state slot s (ycopy, if given, also
+// receives the predictor: the first iterate of a device-controlled attempt).
+struct PrepareParams {
+  int accept, k_acc, transform, k, predict;
+  const double2* dacc;
+  const double (*R)[kNdfMaxOrder + 1];
+};
+
+__device__ inline void prepare_element(const NdfArgs& a, const PrepareParams& pp, int64_t s,
+                                       double2* ycopy) {
+  const int k = pp.k;
   double2 D[kNdfDepth];
 #pragma unroll
   for (int j = 0; j < kNdfDepth; ++j) D[j] = (j < a.depth) ? a.D[(int64_t)j * a.S + s] : zero2();
-  if (accept) {
+  if (pp.accept) {
     // nabla^{k+1} y_{n+1} = d, nabla^{k+2} y_{n+1} = d - nabla^{k+1} y_n,
     // nabla^j y_{n+1} = nabla^j y_n + nabla^{j+1} y_{n+1}
-    const int ka = ctl ? ctl->prep_k_acc : a.k_acc;
-    const double2 d = ctl ? a.dsel[ctl->prep_dsel][s] : a.dacc[s];
+    const int ka = pp.k_acc;
+    const double2 d = pp.dacc[s];
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j)
       if (j == ka + 2) D[j] = make_double2(d.x - D[j - 1].x, d.y - D[j - 1].y);
@@ -93,7 +48,7 @@ __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
     for (int j = kNdfDepth - 2; j >= 0; --j)
       if (j <= ka) D[j] = make_double2(D[j].x + D[j + 1].x, D[j].y + D[j + 1].y);
   }
-  if (transform) {
+  if (pp.transform) {
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j) {
       double2 v = zero2();
@@ -101,19 +56,19 @@ __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
 #pragma unroll
         for (int i = 0; i <= kNdfMaxOrder; ++i)
           if (i >= j && i <= k) {
-            v.x += R[j][i] * D[i].x;
-            v.y += R[j][i] * D[i].y;
+            v.x += pp.R[j][i] * D[i].x;
+            v.y += pp.R[j][i] * D[i].y;
           }
       }
       D[j] = v;  // rows are computed from D[i >= j] before D[j] is replaced
     }
   }
-  if (accept || transform) {
+  if (pp.accept || pp.transform) {
 #pragma unroll
     for (int j = 0; j < kNdfDepth; ++j)
       if (j < a.depth) a.D[(int64_t)j * a.S + s] = D[j];
   }
-  if (predict) {
+  if (pp.predict) {
     double2 y = D[0], p = zero2();
 #pragma unroll
     for (int j = 1; j <= kNdfMaxOrder; ++j)
@@ -125,6 +80,82 @@ __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
       }
     a.y0[s] = y;
     a.psi[s] = p;
+    if (ycopy) ycopy[s] = y;
+  }
+}
+
+// Host-controlled prepare (its parameters in the arguments); clears the sweep norms.
+__global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < a.nnorms) a.norms[threadIdx.x] = 0ull;
+  if (blockIdx.x == 0 && a.done && (int)threadIdx.x < a.nnorms / 4) a.done[threadIdx.x] = 0u;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  PrepareParams pp{a.accept, a.k_acc, a.transform, a.k, a.predict, a.dacc, a.R};
+  prepare_element(a, pp, s, nullptr);
+}
+
+// Opens sweep slot `sel` of a device-controlled run. Every workgroup copies the
+// controller state and reduces the previous sweep's norm copies, thread 0 runs
+// the controller (the same inputs give every workgroup the same result), and
+// when an attempt has just been opened every workgroup prepares its share of the
+// state; workgroup 0 writes the new state and the attempt record.
+__global__ __launch_bounds__(256) void k_ndf_step(NdfArgs a, NdfStepArgs st) {
+  static_assert(kNdfSpread == 64, "one copy per lane of wave 0");
+  __shared__ NdfCtl sc;
+  __shared__ int prep;
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(st.ctl_in);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(&sc);
+  unsigned long long w[(kCtlWords + 255) / 256];
+#pragma unroll
+  for (int i = 0; i < (kCtlWords + 255) / 256; ++i) {
+    const int j = threadIdx.x + 256 * i;
+    if (j < kCtlWords) w[i] = src[j];
+  }
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      v[q] = __longlong_as_double((long long)st.spread_in[threadIdx.x * kNdfSpreadStride + q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o, 64));
+  }
+#pragma unroll
+  for (int i = 0; i < (kCtlWords + 255) / 256; ++i) {
+    const int j = threadIdx.x + 256 * i;
+    if (j < kCtlWords) dst[j] = w[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int p = 0;
+    if (sc.fresh) {
+      sc.fresh = 0;
+      p = sc.running;
+    } else if (sc.running) {
+      double row[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) row[q] = sqrt(v[q]);
+      const int r = ndf_decide(sc, row, st.sched, 1 - st.sel);
+      if (r == NDF_ENDED) {
+        if (blockIdx.x == 0) st.log[(sc.nlog - 1) % kNdfLogCap] = sc.rec;
+        p = sc.running;
+      }
+    }
+    prep = p;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t w2 = s0; w2 < a.spread_words; w2 += stride) st.spread_clear[w2] = 0ull;
+  if (prep) {
+    PrepareParams pp{sc.prep_accept, sc.prep_k_acc,   sc.prep_transform, sc.prep_k,
+                     sc.prep_predict, a.dsel[sc.prep_dsel], sc.prepR};
+    for (int64_t s = s0; s < a.S; s += stride) prepare_element(a, pp, s, a.yout);
+  }
+  if (blockIdx.x == 0) {
+    const unsigned long long* from = reinterpret_cast<const unsigned long long*>(&sc);
+    unsigned long long* to = reinterpret_cast<unsigned long long*>(st.ctl_out);
+    for (int j = threadIdx.x; j < kCtlWords; j += blockDim.x) to[j] = from[j];
   }
 }
 
@@ -173,8 +204,7 @@ __device__ inline void publish_norms(const NdfArgs& a) {
 // wt = max(|y_n|, |y_i|, atol/rtol) per complex coefficient (squared here).
 __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
   const NdfCtl* ctl = a.ctl;
-  if (ctl &&
-      __hip_atomic_load(&ctl->gates[a.sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+  if (ctl && __hip_atomic_load(&ctl->running, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
     return;
   const int ak_k = ctl ? ctl->k : a.k;
   const double h = ctl ? ctl->h : a.h;
@@ -206,7 +236,8 @@ __global__ __launch_bounds__(256) void k_ndf_correct(GroupView g, NdfArgs a) {
       if (l == 0) d = zero2();
       if (m == 0) d.y = 0.0;
       const double2 y = make_double2(y0.x + d.x, y0.y + d.y);
-      const double2 dp = a.dprev ? a.dprev[s] : zero2();
+      // device-controlled: no previous correction on an attempt's first sweep
+      const double2 dp = (a.dprev && !(ctl && ctl->sweep == 0)) ? a.dprev[s] : zero2();
       a.dout[s] = d;
       a.yout[s] = y;
       const double wt2 = fmax(fmax(abs2(D0), abs2(y)), a.thr2);
@@ -234,10 +265,9 @@ hipError_t launch_ndf_prepare(const NdfArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ndf_decide(NdfCtl* c, const unsigned long long* spread_row, int slot,
-                             nse_adaptive_record* log, const nse_forcing_schedule& sched,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_ndf_decide, dim3(1), dim3(64), 0, s, c, spread_row, slot, log, sched);
+hipError_t launch_ndf_step(const NdfArgs& a, const NdfStepArgs& st, hipStream_t s) {
+  const int64_t blocks = (a.S + 255) / 256;
+  hipLaunchKernelGGL(k_ndf_step, dim3((unsigned)blocks), dim3(256), 0, s, a, st);
   return hipGetLastError();
 }
 

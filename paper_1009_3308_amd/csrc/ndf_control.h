@@ -102,10 +102,12 @@ struct NdfCtl {
   int sweep;
   double dd1, dd_prev;
   double fscale;  // s(t + h)
-  // device-controlled runs: each captured attempt sequence is a prepare and
-  // K sweep slots; a slot's kernels run only while its gate is open
-  int gates[kMaxNewton];  // gates[i]: sweep i + 1 of the open attempt is due
-  int open;    // an attempt is open (its prepare is due)
+  // device-controlled runs: a captured sequence of sweep slots, each a step
+  // kernel (controller on the previous sweep's norms, and the prepare of a newly
+  // opened attempt) and the chain with the corrector; the chain runs while
+  // `running` (an attempt is open)
+  int running;
+  int fresh;   // the host opened the attempt: the next step kernel only prepares
   int done;    // t reached t_end
   int status;  // NDF_OK or the NDF_FAIL_* that stopped the run
   int prep_accept, prep_k_acc, prep_dsel, prep_transform, prep_k, prep_predict;
@@ -338,12 +340,10 @@ __host__ __device__ inline void ndf_take_prepare(NdfCtl& c, int predict) {
 }
 
 // Opens the next attempt of a device-controlled run (host before the first
-// one, the deciding kernel after each): its step size, forcing scale and
-// prepare snapshot, the prepare and the first sweep slot due; or the end of the
-// run (done, or the failure in status).
+// one, the step kernel after each): its step size, forcing scale and prepare
+// snapshot; or the end of the run (done, or the failure in status).
 __host__ __device__ inline void ndf_open_attempt(NdfCtl& c, const nse_forcing_schedule& sched) {
-  for (int i = 0; i < kMaxNewton; ++i) c.gates[i] = 0;
-  c.open = 0;
+  c.running = 0;
   const int r = ndf_begin_attempt(c);
   if (r == NDF_STOP) {
     c.done = 1;
@@ -352,34 +352,39 @@ __host__ __device__ inline void ndf_open_attempt(NdfCtl& c, const nse_forcing_sc
   } else {
     c.fscale = schedule_scale(sched, c.t + c.h);
     ndf_take_prepare(c, 1);
-    c.gates[0] = 1;
-    c.open = 1;
+    c.running = 1;
   }
 }
 
-// After sweep slot `slot` of a device-controlled run: the controller on the
-// sweep's norms; the next slot's gate, or the attempt's record and the next
-// attempt. Returns NDF_ENDED when an attempt ended (its record in c.rec).
-__host__ __device__ inline int ndf_decide(NdfCtl& c, int slot, const double row[4],
-                                          const nse_forcing_schedule& sched) {
+// Controller of a device-controlled run after a sweep whose correction went to
+// buffer `dsel_last`: another sweep, or the attempt's end (record in c.rec)
+// and the next attempt opened. Returns NDF_CONTINUE, NDF_ENDED or -NDF_FAIL_*.
+__host__ __device__ inline int ndf_decide(NdfCtl& c, const double row[4],
+                                          const nse_forcing_schedule& sched, int dsel_last) {
   const int r = ndf_after_sweep(c, row);
-  if (r == NDF_CONTINUE) {
-    c.gates[slot] = 0;
-    c.gates[slot + 1] = 1;
-    return r;
-  }
+  if (r == NDF_CONTINUE) return r;
   if (r < 0) {
-    for (int i = 0; i < kMaxNewton; ++i) c.gates[i] = 0;
-    c.open = 0;
+    c.running = 0;
     c.status = -r;
     return r;
   }
+  if (c.pend_accept) c.pend_dsel = dsel_last;
   ndf_open_attempt(c, sched);
   return NDF_ENDED;
 }
 
-hipError_t launch_ndf_decide(NdfCtl* c, const unsigned long long* spread_row, int slot,
-                             nse_adaptive_record* log, const nse_forcing_schedule& sched,
-                             hipStream_t s);
+// The step kernel of sweep slot j (buffer parity sel = j % 2): reads the
+// controller state from ctl_in, writes it to ctl_out, reduces the norms of the
+// previous slot (spread_in), clears this slot's norms (spread_clear).
+struct NdfStepArgs {
+  const NdfCtl* ctl_in;
+  NdfCtl* ctl_out;
+  const unsigned long long* spread_in;
+  unsigned long long* spread_clear;
+  int sel;
+  nse_adaptive_record* log;
+  nse_forcing_schedule sched;
+};
+hipError_t launch_ndf_step(const NdfArgs& a, const NdfStepArgs& st, hipStream_t s);
 
 }  // namespace nse

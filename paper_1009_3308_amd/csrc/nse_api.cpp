@@ -166,7 +166,7 @@ struct nse_ctx {
   NdfCtl* d_ctl = nullptr;               // device copy during device-controlled runs
   NdfCtl* h_ctl = nullptr;               // pinned staging of its copies
   nse_adaptive_record* d_log = nullptr;  // [kNdfLogCap] ring of attempt records
-  unsigned long long* d_spread = nullptr;  // [kMaxNewton][kNdfSpreadRow] sweep norm copies
+  unsigned long long* d_spread = nullptr;  // [2][kNdfSpreadRow] sweep norm copies (slot parity)
   hipGraph_t ad_graph = nullptr;         // captured attempt sequence
   hipGraphExec_t ad_exec = nullptr;
   hipStream_t cap_stream = nullptr;      // private stream it is captured on (the
@@ -662,8 +662,9 @@ nse_status enqueue_nonlinear_adjoint(nse_ctx* c, SynthInput in, const double2* n
 // Adaptive NDF integrator. The controller (ndf_control.h) runs on the host when
 // a forcing callback has to be called per time level, else on the device.
 
-constexpr int kAttemptsPerGraph = 4;     // attempts in one captured sequence
+constexpr int kSlotsPerGraph = 16;       // sweep slots in one captured sequence (even)
 constexpr int kMaxGraphsPerBatch = 32;   // sequences enqueued between two waits
+static_assert(kSlotsPerGraph % 2 == 0, "slots alternate between two state buffers");
 
 nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
   if (c->d_ndf && c->ndf_depth == depth) return NSE_OK;
@@ -681,11 +682,10 @@ nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
     NSE_HIP(c, hipHostGetDevicePointer((void**)&c->d_pub, c->h_pub, 0));
   }
   if (!c->d_ctl) {
-    NSE_HIP(c, hipMalloc((void**)&c->d_ctl, sizeof(NdfCtl)));
+    NSE_HIP(c, hipMalloc((void**)&c->d_ctl, 2 * sizeof(NdfCtl)));  // read / written by alternate slots
     NSE_HIP(c, hipHostMalloc((void**)&c->h_ctl, sizeof(NdfCtl), hipHostMallocDefault));
     NSE_HIP(c, hipMalloc((void**)&c->d_log, sizeof(nse_adaptive_record) * kNdfLogCap));
-    NSE_HIP(c, hipMalloc((void**)&c->d_spread,
-                         sizeof(unsigned long long) * kMaxNewton * kNdfSpreadRow));
+    NSE_HIP(c, hipMalloc((void**)&c->d_spread, sizeof(unsigned long long) * 2 * kNdfSpreadRow));
   }
   return NSE_OK;
 }
@@ -786,7 +786,7 @@ nse_status ndf_eval(nse_ctx* c, const double2* src, const int* gate = nullptr) {
 // norms; device-controlled (ctl): those from the control block, gated by the
 // sweep slot (k_ndf_decide then runs the controller).
 nse_status ndf_correct(nse_ctx* c, int mode, int sweep, const double2* dprev, double2* dout,
-                       NdfCtl* ctl = nullptr) {
+                       const NdfCtl* ctl = nullptr) {
   const NdfCtl& k = c->ad.c;
   NdfArgs a = ndf_args(c);
   a.mode = mode;
@@ -799,6 +799,7 @@ nse_status ndf_correct(nse_ctx* c, int mode, int sweep, const double2* dprev, do
   a.yout = ndf_buf(c, 2);
   a.h = mode == NDF_RHS ? 0.0 : k.h;
   a.ak = ndf_alpha(k.k);
+  // device-controlled: `sweep` is the slot parity, which selects the norm row
   a.nrow = ctl ? c->d_spread + (int64_t)sweep * kNdfSpreadRow : c->d_norms + 4 * sweep;
   a.sweep = sweep;
   a.pub = c->d_pub;
@@ -822,31 +823,33 @@ bool ndf_fusable(const nse_ctx* c) {
   return g.precision != NSE_PREC_BF16X3 && !(g.precision == NSE_PREC_FP64 && g.mb_anal >= 2);
 }
 
-// Sweep `sweep` (0-based) of a device-controlled attempt with the corrector in
-// the analysis epilogue.
-nse_status ndf_sweep_fused(nse_ctx* c, int sweep) {
-  const double2* src = sweep == 0 ? ndf_buf(c, 0) : ndf_buf(c, 2);
+// The chain of device-controlled sweep slot parity `sel` with the corrector in
+// the analysis epilogue: the iterate y in, the correction to buffer sel (the
+// previous one in 1 - sel), the norms to spread row sel, the control block
+// written by the slot's k_ndf_step.
+nse_status ndf_sweep_fused(nse_ctx* c, int sel) {
+  const NdfCtl* ctl = c->d_ctl + (1 - sel);
   SynthInput in{};
   in.nsrc = 1;
-  in.src[0] = src;
+  in.src[0] = ndf_buf(c, 2);
   in.coef[0] = 1.0;
   in.coriolis = 2.0 * c->params.omega * std::sqrt(4.0 * kPi / 3.0);
   AnalOutput out{};
   out.mode = ANAL_NDF;
   out.state_count = c->state_count;
   out.forcing = c->ad.forcing;
-  out.ctl = c->d_ctl;
+  out.ctl = ctl;
   out.D = c->d_ndf;
   out.y0 = ndf_buf(c, 0);
   out.psi = ndf_buf(c, 1);
-  out.dprev = sweep == 0 ? nullptr : ndf_buf(c, 3 + ((sweep - 1) & 1));
-  out.dout = ndf_buf(c, 3 + (sweep & 1));
+  out.dprev = ndf_buf(c, 3 + (1 - sel));
+  out.dout = ndf_buf(c, 3 + sel);
   out.yout = ndf_buf(c, 2);
-  out.nrow = c->d_spread + (int64_t)sweep * kNdfSpreadRow;
+  out.nrow = c->d_spread + (int64_t)sel * kNdfSpreadRow;
   out.kmax = c->ad.p.max_order;
   const double r = c->ad.p.atol / c->ad.p.rtol;
   out.thr2 = r * r;
-  return enqueue_chain(c, in, out, &c->d_ctl->gates[sweep]);
+  return enqueue_chain(c, in, out, &ctl->running);
 }
 
 nse_status ndf_failure(nse_ctx* c, int code) {
@@ -892,9 +895,11 @@ nse_status ndf_attempt_host(nse_ctx* c) {
   return fail(c, NSE_ERR_STATE, "attempt did not end after %d sweeps", K);
 }
 
-// Captures kAttemptsPerGraph attempts of the device-controlled run: each is the
-// prepare (run while an attempt is open) and max_newton sweep slots (chain with
-// the corrector, then k_ndf_decide), each slot's kernels gated by its gate.
+// Captures kSlotsPerGraph sweep slots of the device-controlled run. Slot j
+// (parity sel = j % 2): k_ndf_step (controller state from buffer sel to 1 - sel,
+// norms of the previous slot from spread row 1 - sel, this slot's row cleared,
+// the prepare of a newly opened attempt), then the chain with the corrector,
+// run while an attempt is open. Every slot is a sweep while the run lasts.
 nse_status capture_attempt_graph(nse_ctx* c) {
   if (!c->cap_stream) NSE_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   const hipStream_t user_stream = c->stream;
@@ -906,33 +911,34 @@ nse_status capture_attempt_graph(nse_ctx* c) {
   } restore{c, user_stream};
   NSE_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   nse_status s = NSE_OK;
-  const int K = c->ad.c.K;
   const bool fused = ndf_fusable(c);
-  for (int at = 0; at < kAttemptsPerGraph && s == NSE_OK; ++at) {
+  for (int j = 0; j < kSlotsPerGraph && s == NSE_OK; ++j) {
+    const int sel = j & 1;
     NdfArgs a = ndf_args(c);
-    a.ctl = c->d_ctl;
+    a.yout = ndf_buf(c, 2);
     a.dsel[0] = ndf_buf(c, 3);
     a.dsel[1] = ndf_buf(c, 4);
-    a.spread = c->d_spread;
-    a.spread_words = (int64_t)K * kNdfSpreadRow;
-    hipError_t e = launch_ndf_prepare(a, c->stream);
+    a.spread_words = kNdfSpreadRow;
+    NdfStepArgs st{};
+    st.ctl_in = c->d_ctl + sel;
+    st.ctl_out = c->d_ctl + (1 - sel);
+    st.spread_in = c->d_spread + (int64_t)(1 - sel) * kNdfSpreadRow;
+    st.spread_clear = c->d_spread + (int64_t)sel * kNdfSpreadRow;
+    st.sel = sel;
+    st.log = c->d_log;
+    st.sched = c->ad.sched;
+    const hipError_t e = launch_ndf_step(a, st, c->stream);
     if (e != hipSuccess) {
-      s = hip_fail(c, e, "launch_ndf_prepare");
+      s = hip_fail(c, e, "launch_ndf_step");
       break;
     }
-    for (int i = 1; i <= K && s == NSE_OK; ++i) {
-      if (fused) {
-        s = ndf_sweep_fused(c, i - 1);
-      } else {
-        s = ndf_eval(c, i == 1 ? ndf_buf(c, 0) : ndf_buf(c, 2), &c->d_ctl->gates[i - 1]);
-        if (s == NSE_OK)
-          s = ndf_correct(c, NDF_SWEEP, i - 1, i == 1 ? nullptr : ndf_buf(c, 3 + ((i - 2) & 1)),
-                          ndf_buf(c, 3 + ((i - 1) & 1)), c->d_ctl);
-      }
-      if (s != NSE_OK) break;
-      e = launch_ndf_decide(c->d_ctl, c->d_spread + (int64_t)(i - 1) * kNdfSpreadRow, i - 1,
-                            c->d_log, c->ad.sched, c->stream);
-      if (e != hipSuccess) s = hip_fail(c, e, "launch_ndf_decide");
+    if (fused) {
+      s = ndf_sweep_fused(c, sel);
+    } else {
+      const NdfCtl* ctl = c->d_ctl + (1 - sel);
+      s = ndf_eval(c, ndf_buf(c, 2), &ctl->running);
+      if (s == NSE_OK)
+        s = ndf_correct(c, NDF_SWEEP, sel, ndf_buf(c, 3 + (1 - sel)), ndf_buf(c, 3 + sel), ctl);
     }
   }
   hipGraph_t gr = nullptr;
@@ -967,15 +973,19 @@ nse_status advance_device(nse_ctx* c) {
   ndf_open_attempt(k, ad.sched);  // the first attempt; the device opens the others
   if (k.status) return ndf_failure(c, k.status);
   if (k.done) return NSE_OK;
+  k.fresh = 1;  // the first slot's step kernel prepares it
   *c->h_ctl = k;
   NSE_HIP(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(NdfCtl), hipMemcpyHostToDevice, c->stream));
   long long read = k.nlog;
   std::vector<nse_adaptive_record> recs;
   for (;;) {
-    // enough attempts for the remaining interval at the current step, plus a
-    // margin for rejections; the surplus ones find the gate closed
-    const double need = (k.t_end - k.t) / k.h * 1.1 + 2.0;
-    int graphs = (int)std::min<double>(kMaxGraphsPerBatch, std::ceil(need / kAttemptsPerGraph));
+    // enough sweeps for the remaining interval at the current step and the mean
+    // sweeps per attempt so far, plus a margin for rejections; the slots after
+    // the end find no open attempt
+    const double attempts = std::max<double>(1.0, (double)(k.nlog > 0 ? k.nlog : 1));
+    const double per = k.nlog > 0 ? (double)(k.evaluations - 1) / attempts : (double)k.K;
+    const double need = ((k.t_end - k.t) / k.h * 1.1 + 1.0) * std::max(1.0, per);
+    int graphs = (int)std::min<double>(kMaxGraphsPerBatch, std::ceil(need / kSlotsPerGraph));
     graphs = std::max(graphs, 1);
     for (int i = 0; i < graphs; ++i) NSE_HIP(c, hipGraphLaunch(c->ad_exec, c->stream));
     NSE_HIP(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(NdfCtl), hipMemcpyDeviceToHost,

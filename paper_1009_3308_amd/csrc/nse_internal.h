@@ -144,7 +144,7 @@ struct AnalOutput {
   // y = y0 + d, and the sweep's four weighted max norms (as k_ndf_correct)
   const NdfCtl* ctl;
   const double2* D;          // [kmax + 3][state_count] backward differences
-  const double2 *y0, *psi, *dprev;  // dprev null on the first sweep
+  const double2 *y0, *psi, *dprev;  // dprev: read only when the attempt has had a sweep
   double2 *dout, *yout;
   unsigned long long* nrow;  // the sweep's spread norm row (squares, IEEE bits, atomic max)
   int kmax;
@@ -191,14 +191,12 @@ struct NdfArgs {
   unsigned int* done;          // [max sweeps] workgroup counters, zeroed by k_ndf_prepare
   unsigned long long* pub;     // host-mapped: [4 x max sweeps] norms, then the sequence word
   unsigned long long seq;
-  // device-controlled integration: the attempt's parameters come from the
-  // control block (k_ndf_prepare: its prepare snapshot, run while an attempt is
-  // open; k_ndf_correct: h, k and the forcing scale, run while the gate of
-  // sweep slot `sweep` is open)
+  // device-controlled integration (k_ndf_step, and k_ndf_correct with h, the
+  // order and the forcing scale from the control block ctl, run while an
+  // attempt is open)
   const NdfCtl* ctl;
   double2* dsel[2];            // the two correction buffers (accepted one chosen by the control block)
-  unsigned long long* spread;  // the sweeps' spread norm rows (nrow points into it), zeroed
-  int64_t spread_words;        // by k_ndf_prepare
+  int64_t spread_words;        // k_ndf_step: words of a spread norm row
 };
 
 // Launchers (each enqueues on `s` and returns the launch status).

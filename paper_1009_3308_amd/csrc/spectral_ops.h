@@ -133,7 +133,7 @@ __device__ inline void load_degree_inputs(const GroupView& g, const AnalOutput& 
     in[1] = out.D[slot];
     in[2] = out.y0[slot];
     in[3] = out.psi[slot];
-    in[4] = out.dprev ? out.dprev[slot] : z;
+    in[4] = (out.dprev && out.ctl->sweep != 0) ? out.dprev[slot] : z;  // none on a first sweep
     in[5] = q > 1 ? out.D[(int64_t)q * S + slot] : z;
     in[6] = q < out.kmax ? out.D[(int64_t)(q + 1) * S + slot] : z;
     return;
