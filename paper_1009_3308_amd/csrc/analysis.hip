@@ -171,7 +171,12 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       finish_degree_from<true>(g, out, b, m, k, (double)sr[0], (double)si[0],
                                pre + (k - kt) * kDegreeInputs, v);
     const int copy = ((blockIdx.y * gridDim.x + blockIdx.x) * kAnalWaves + wave) % kNdfSpread;
-    wave_max4_atomic(v, out.nrow + copy * kNdfSpreadStride);
+    const double mx = lane_max4(v);  // lane 16 q: the wave's maximum of v[q]
+    if ((lane & 15) == 0) {
+      unsigned long long bits = (unsigned long long)__double_as_longlong(mx);
+      if (mx != mx) bits = 0x7ff8000000000000ull;  // one positive NaN pattern
+      atomicMax(out.nrow + copy * kNdfSpreadStride + (lane >> 4), bits);
+    }
   } else {
     if ((lane & 3) != 0) return;
     if (k > N - m) return;

@@ -101,4 +101,39 @@ __device__ inline void lane_butterfly16(T (&xr)[kButterfly], T (&xi)[kButterfly]
   xi[0] += lane_dpp<kDppQuadXor1>(xi[0]);
 }
 
+// Maximum over the 64 lanes of four non-negative doubles (NaN kept), with the
+// exchanges of lane_butterfly16: after the two lane-half swaps row r (lanes
+// 16 r .. 16 r + 15) holds partial maxima of v[r]; the row mirror, half-row
+// mirror and the two quad permutations complete each row. On return lane 16 r
+// holds the maximum of v[r].
+__device__ inline double lane_nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
+__device__ inline double lane_swap_max(double a, double b, bool rows16) {
+  const unsigned long long ai = __double_as_longlong(a), bi = __double_as_longlong(b);
+  unsigned lo0, lo1, hi0, hi1;
+  if (rows16) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ai, (unsigned)bi, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane16_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
+    lo0 = lo[0], lo1 = lo[1], hi0 = hi[0], hi1 = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ai, (unsigned)bi, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane32_swap((unsigned)(ai >> 32), (unsigned)(bi >> 32), false, false);
+    lo0 = lo[0], lo1 = lo[1], hi0 = hi[0], hi1 = hi[1];
+  }
+  const double a2 = __longlong_as_double((long long)(((unsigned long long)hi0 << 32) | lo0));
+  const double b2 = __longlong_as_double((long long)(((unsigned long long)hi1 << 32) | lo1));
+  return lane_nanmax(a2, b2);
+}
+__device__ inline double lane_max4(const double (&v)[4]) {
+  const double w0 = lane_swap_max(v[0], v[2], false);  // lanes 0..31: v[0], 32..63: v[2]
+  const double w1 = lane_swap_max(v[1], v[3], false);
+  double u = lane_swap_max(w0, w1, true);               // row r: v[r]
+  u = lane_nanmax(u, lane_dpp<kDppRowMirror>(u));
+  u = lane_nanmax(u, lane_dpp<kDppRowHalfMirror>(u));
+  u = lane_nanmax(u, lane_dpp<kDppQuadXor2>(u));
+  u = lane_nanmax(u, lane_dpp<kDppQuadXor1>(u));
+  return u;
+}
+
 }  // namespace nse

@@ -5,6 +5,7 @@
 // device-controlled run k_ndf_step opens every sweep slot: the controller of
 // ndf_control.h on the previous sweep's norms and, when an attempt has just
 // been opened, its prepare.
+#include "lane_ops.h"
 #include "ndf_control.h"
 
 namespace nse {
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(256) void k_ndf_step(NdfArgs a, NdfStepArgs st) {
   static_assert(kNdfSpread == 64, "one copy per lane of wave 0");
   __shared__ NdfCtl sc;
   __shared__ int prep;
+  __shared__ double norm[4];
   const unsigned long long* src = reinterpret_cast<const unsigned long long*>(st.ctl_in);
   unsigned long long* dst = reinterpret_cast<unsigned long long*>(&sc);
   unsigned long long w[(kCtlWords + 255) / 256];
@@ -111,14 +113,13 @@ __global__ __launch_bounds__(256) void k_ndf_step(NdfArgs a, NdfStepArgs st) {
     const int j = threadIdx.x + 256 * i;
     if (j < kCtlWords) w[i] = src[j];
   }
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (threadIdx.x < 64) {
+    double v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       v[q] = __longlong_as_double((long long)st.spread_in[threadIdx.x * kNdfSpreadStride + q]);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o, 64));
+    const double mx = lane_max4(v);  // lane 16 q: the maximum of v[q]
+    if ((threadIdx.x & 15) == 0) norm[threadIdx.x >> 4] = mx;
   }
 #pragma unroll
   for (int i = 0; i < (kCtlWords + 255) / 256; ++i) {
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_ndf_step(NdfArgs a, NdfStepArgs st) {
     } else if (sc.running) {
       double row[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) row[q] = sqrt(v[q]);
+      for (int q = 0; q < 4; ++q) row[q] = sqrt(norm[q]);
       const int r = ndf_decide(sc, row, st.sched, 1 - st.sel);
       if (r == NDF_ENDED) {
         if (blockIdx.x == 0) st.log[(sc.nlog - 1) % kNdfLogCap] = sc.rec;

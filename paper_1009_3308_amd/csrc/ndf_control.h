@@ -305,24 +305,6 @@ __host__ __device__ inline int ndf_after_sweep(NdfCtl& c, const double row[4]) {
 // max that keeps a NaN operand (fmax would drop it)
 __host__ __device__ inline double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
 
-// Max of four non-negative values over a wave (all 64 lanes active), then one
-// atomic max per value by lane 0 into out[0..3]. Non-negative IEEE doubles order
-// like their bit patterns and a NaN sorts above +inf, so a non-finite norm
-// reaches the controller.
-__device__ inline void wave_max4_atomic(double v[4], unsigned long long* out) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o, 64));
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      unsigned long long bits = (unsigned long long)__double_as_longlong(v[q]);
-      if (v[q] != v[q]) bits = 0x7ff8000000000000ull;  // one positive NaN pattern
-      atomicMax(out + q, bits);
-    }
-  }
-}
-
 // Parameters of the next k_ndf_prepare from the pending work (predict: the
 // predictor of order k follows).
 __host__ __device__ inline void ndf_take_prepare(NdfCtl& c, int predict) {

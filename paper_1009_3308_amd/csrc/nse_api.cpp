@@ -167,8 +167,13 @@ struct nse_ctx {
   NdfCtl* h_ctl = nullptr;               // pinned staging of its copies
   nse_adaptive_record* d_log = nullptr;  // [kNdfLogCap] ring of attempt records
   unsigned long long* d_spread = nullptr;  // [2][kNdfSpreadRow] sweep norm copies (slot parity)
-  hipGraph_t ad_graph = nullptr;         // captured attempt sequence
+  hipGraph_t ad_graph = nullptr;         // captured sweep-slot sequence
   hipGraphExec_t ad_exec = nullptr;
+  struct {                               // what its kernel arguments name
+    const double2* forcing;
+    nse_forcing_schedule sched;
+    int K;
+  } ad_key{};
   hipStream_t cap_stream = nullptr;      // private stream it is captured on (the
                                          // context stream may be the null stream)
   double2* d_diag = nullptr;  // inertial manifold: band-limited input, its nonlinear term
@@ -666,8 +671,11 @@ constexpr int kSlotsPerGraph = 16;       // sweep slots in one captured sequence
 constexpr int kMaxGraphsPerBatch = 32;   // sequences enqueued between two waits
 static_assert(kSlotsPerGraph % 2 == 0, "slots alternate between two state buffers");
 
+void drop_attempt_graph(nse_ctx* c);
+
 nse_status ensure_ndf_buffers(nse_ctx* c, int depth) {
   if (c->d_ndf && c->ndf_depth == depth) return NSE_OK;
+  drop_attempt_graph(c);  // names the old buffers
   (void)hipFree(c->d_ndf);
   c->d_ndf = nullptr;
   c->ndf_depth = 0;
@@ -956,6 +964,9 @@ nse_status capture_attempt_graph(nse_ctx* c) {
   }
   c->ad_graph = gr;
   c->ad_exec = ex;
+  c->ad_key.forcing = c->ad.forcing;
+  c->ad_key.sched = c->ad.sched;
+  c->ad_key.K = c->ad.c.K;
   return NSE_OK;
 }
 
@@ -1667,7 +1678,12 @@ static nse_status adaptive_begin(nse_ctx* ctx, const double* alpha0, double t0,
   k.K = p.max_newton;
   k.t = t0;
   k.k = 1;
-  drop_attempt_graph(ctx);  // its arguments name this run's forcing and schedule
+  // the captured slot sequence names the forcing, the schedule and max_newton
+  if (ctx->ad_exec && (ctx->ad_key.forcing != ad.forcing || ctx->ad_key.K != k.K ||
+                       std::memcmp(&ctx->ad_key.sched, &ad.sched, sizeof(ad.sched)) != 0)) {
+    NSE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    drop_attempt_graph(ctx);
+  }
   nse_status s = ensure_ndf_buffers(ctx, p.max_order + 3);
   if (s != NSE_OK) return s;
   const size_t bytes = sizeof(double2) * (size_t)ctx->state_count;
