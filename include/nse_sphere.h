@@ -195,6 +195,30 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist,
                             const double* forcing, int64_t step,
                             double* hist_bar);
 
+/* nsteps steps of nse_step (eq. (ode_disc)) on a trajectory buffer: traj is a
+ * device array of nsteps + order + 1 states; on entry traj[nsteps + j] holds
+ * alpha_{step0 - j} (j = 0..order: the history of nse_step), and step
+ * step0 + i (i = 0..nsteps-1) reads its history from traj[nsteps - i ..]
+ * (newest first) and writes its new state to traj[nsteps - i - 1]. On return
+ * traj[0] is the final state and traj[nsteps - i ..] is the history before step
+ * step0 + i, as nse_step_adjoint_trajectory reads it. The results equal those
+ * of nse_step (the same kernels; the new state is stored one slot lower
+ * instead of rotating the history). With NSE_FLAG_GRAPH the steps with fixed
+ * coefficients (index > order) replay one captured graph per (traj, forcing,
+ * nsteps, step0 range). NSE_ERR_ARG for NULL traj or negative step0, nsteps. */
+nse_status nse_step_trajectory(nse_ctx* ctx, double* traj, const double* forcing,
+                               int64_t step0, int32_t nsteps);
+
+/* The adjoint of nse_step_trajectory over the same traj (unchanged since):
+ * hist_bar ([order+1][state], device) holds dL/d(history after step
+ * step0 + nsteps - 1) on input and dL/d(history before step step0) on output,
+ * the step adjoints of nse_step_adjoint applied from the last step back, each
+ * reading its history from traj. Requires newton_iters == 1; hist_bar may not
+ * overlap traj. With NSE_FLAG_GRAPH the fixed-coefficient steps replay one
+ * captured graph per (traj, hist_bar, nsteps, step0 range). */
+nse_status nse_step_adjoint_trajectory(nse_ctx* ctx, const double* traj, const double* forcing,
+                                       int64_t step0, int32_t nsteps, double* hist_bar);
+
 /* Grid values of u_theta, u_phi and zeta for every member: device array
  * [member][3][nlat][M] of doubles (latitudes north to south, longitudes
  * phi_j = 2 pi j / M). */

@@ -41,7 +41,7 @@ EXPORTS = (
     "nse_adaptive_begin", "nse_adaptive_begin_scheduled", "nse_adaptive_advance",
     "nse_adaptive_log",
     "nse_energy_spectrum", "nse_synthesize_psi", "nse_inertial_manifold",
-    "nse_nonlinear_adjoint_noalloc",
+    "nse_nonlinear_adjoint_noalloc", "nse_step_trajectory", "nse_step_adjoint_trajectory",
 )
 
 ATTEMPT_ACCEPTED, ATTEMPT_ERROR_FAIL, ATTEMPT_NEWTON_FAIL = 0, 1, 2
@@ -125,6 +125,8 @@ def lib():
         "nse_nonlinear_adjoint": (st, [vp, dp, dp, dp]),
         "nse_nonlinear_adjoint_noalloc": (st, [vp, dp, dp, dp]),
         "nse_step_adjoint": (st, [vp, dp, dp, i64, dp]),
+        "nse_step_trajectory": (st, [vp, dp, dp, i64, i32]),
+        "nse_step_adjoint_trajectory": (st, [vp, dp, dp, i64, i32, dp]),
         "nse_synthesize": (st, [vp, dp, dp]),
         "nse_analyze_velocity": (st, [vp, dp, dp]),
         "nse_get_member_blocks": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -298,6 +300,34 @@ class Sphere:
             self._handle(), _ptr(hist, torch.complex128, n, "hist"),
             _ptr(forcing, torch.complex128, self.state_count, "forcing"), int(step),
             _ptr(hist_bar, torch.complex128, n, "hist_bar")), self._h)
+        return hist_bar
+
+    def new_trajectory(self, nsteps: int):
+        """A zeroed trajectory buffer of nsteps + order + 1 states (step_trajectory)."""
+        import torch
+        return torch.zeros(int(nsteps) + self.order + 1, self.state_count,
+                           dtype=torch.complex128, device="cuda")
+
+    def step_trajectory(self, traj, forcing, step0: int, nsteps: int):
+        """nsteps steps on traj: traj[nsteps:] holds the starting history on entry,
+        traj[nsteps - i:] the history before step step0 + i on return."""
+        import torch
+        n = (int(nsteps) + self.order + 1) * self.state_count
+        _check(lib().nse_step_trajectory(
+            self._handle(), _ptr(traj, torch.complex128, n, "traj"),
+            _ptr(forcing, torch.complex128, self.state_count, "forcing"), int(step0),
+            int(nsteps)), self._h)
+        return traj
+
+    def step_adjoint_trajectory(self, traj, forcing, step0: int, nsteps: int, hist_bar):
+        import torch
+        n = (int(nsteps) + self.order + 1) * self.state_count
+        _check(lib().nse_step_adjoint_trajectory(
+            self._handle(), _ptr(traj, torch.complex128, n, "traj"),
+            _ptr(forcing, torch.complex128, self.state_count, "forcing"), int(step0),
+            int(nsteps),
+            _ptr(hist_bar, torch.complex128, (self.order + 1) * self.state_count, "hist_bar")),
+            self._h)
         return hist_bar
 
     def synthesize(self, alpha):

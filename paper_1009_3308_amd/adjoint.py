@@ -4,10 +4,12 @@
 history [alpha0, 0, ..., 0] and returns the final state as a torch tensor that
 takes part in autograd. Its backward pass is the discrete adjoint: the
 history is kept only every `checkpoint_every` steps during the forward run;
-each segment is recomputed forward from its checkpoint (one nse_step per
-step, keeping the histories of the segment), then swept backward with
-nse_step_adjoint. Every step and every adjoint step runs in the HIP library;
-this module only schedules them and keeps the checkpoints.
+each segment is recomputed forward from its checkpoint into a trajectory
+buffer (nse_step_trajectory, which keeps every intermediate history in place),
+then swept backward over that buffer (nse_step_adjoint_trajectory). Both
+replay captured graphs for the fixed-coefficient steps, and one buffer serves
+every segment. Every step and every adjoint step runs in the HIP library; this
+module only schedules the segments and keeps the checkpoints.
 
 Gradients follow torch's convention for complex tensors and a real loss,
 dL/dRe + i dL/dIm, which is the vector-Jacobian product on the stored
@@ -37,14 +39,14 @@ class _Trajectory(torch.autograd.Function):
         sphere, forcing, step0 = ctx.sphere, ctx.forcing, ctx.step0
         hist_bar = sphere.new_history()
         hist_bar[0] = grad_final
+        trajs = {}
         for s, n, start in reversed(ctx.checkpoints):
-            h = start.clone()
-            seg = []
-            for i in range(n):
-                seg.append(h.clone())
-                sphere.step(h, forcing, step0 + s + i, 1)
-            for i in reversed(range(n)):
-                sphere.step_adjoint(seg[i], forcing, step0 + s + i, hist_bar)
+            if n not in trajs:
+                trajs[n] = sphere.new_trajectory(n)
+            tr = trajs[n]
+            tr[n:] = start
+            sphere.step_trajectory(tr, forcing, step0 + s, n)
+            sphere.step_adjoint_trajectory(tr, forcing, step0 + s, n, hist_bar)
         ctx.checkpoints = None
         return hist_bar[0].clone(), None, None, None, None, None
 

@@ -108,6 +108,11 @@ struct Group {
 struct GraphEntry {
   const void* hist = nullptr;
   const void* forcing = nullptr;
+  // trajectory sequences (kind 1 forward, 2 adjoint): the cotangent buffer,
+  // the buffer length and the range of steps captured
+  int kind = 0;
+  const void* aux = nullptr;
+  int64_t n = 0, i0 = 0, i1 = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint64_t used = 0;  // last use, for least-recently-used eviction
@@ -192,7 +197,7 @@ namespace {
 constexpr int kGraphChunk = 10;
 // captured step graphs kept per context (each new history or forcing address
 // captures its own; the least recently used is dropped beyond this)
-constexpr size_t kGraphCache = 4;
+constexpr size_t kGraphCache = 8;
 constexpr double kPi = 3.14159265358979323846;
 
 nse_status fail(nse_ctx* c, nse_status s, const char* fmt, ...) {
@@ -582,7 +587,8 @@ nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out
 }
 
 // Enqueues step k (all fixed-point sweeps) on the context stream.
-nse_status enqueue_step(nse_ctx* c, double2* hist, const double2* forcing, int64_t k) {
+nse_status enqueue_step(nse_ctx* c, double2* hist, const double2* forcing, int64_t k,
+                        bool shift = false) {
   std::vector<double> cc, pi;
   step_scheme(c->params.order, k, cc, pi);
   const int K = c->params.newton_iters;
@@ -611,6 +617,7 @@ nse_status enqueue_step(nse_ctx* c, double2* hist, const double2* forcing, int64
     out.forcing = forcing;
     out.iter = c->d_iter;
     out.nonfinite = (c->params.flags & NSE_FLAG_CHECK_FINITE) ? c->d_flag : nullptr;
+    out.shift = shift ? 1 : 0;
     nse_status s = enqueue_chain(c, in, out);
     if (s != NSE_OK) return s;
   }
@@ -1328,7 +1335,7 @@ namespace {
 static nse_status step_graph(nse_ctx* ctx, double2* h, const double2* f, int64_t k,
                              hipGraphExec_t* out) {
   for (auto& g : ctx->graphs) {
-    if (g.hist == (const void*)h && g.forcing == (const void*)f) {
+    if (g.kind == 0 && g.hist == (const void*)h && g.forcing == (const void*)f) {
       g.used = ++ctx->graph_clock;
       *out = g.exec;
       return NSE_OK;
@@ -1442,17 +1449,13 @@ nse_status nse_nonlinear_adjoint_noalloc(nse_ctx* ctx, const double* alpha, cons
                                    ctx->noalloc_scratch);
 }
 
-nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forcing, int64_t step,
-                            double* hist_bar) {
-  if (!ctx) return NSE_ERR_ARG;
-  (void)forcing;  // the forcing enters affinely and is not differentiated
-  if (!hist || !hist_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
-  if (hist == hist_bar) return fail(ctx, NSE_ERR_ARG, "hist and hist_bar may not alias");
-  if (step < 0) return fail(ctx, NSE_ERR_ARG, "step must be >= 0");
-  if (ctx->params.newton_iters != 1)
-    return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
-  nse_status s = ensure_adjoint_buffers(ctx);
-  if (s != NSE_OK) return s;
+extern "C++" {
+namespace {
+
+// The adjoint of step `step` (one fixed-point sweep) at history `hist`,
+// accumulating into hist_bar.
+nse_status enqueue_step_adjoint(nse_ctx* ctx, const double2* hist, int64_t step,
+                                       double2* hb) {
   std::vector<double> cc, pi;
   step_scheme(ctx->params.order, step, cc, pi);
   AnalOutput st{};
@@ -1464,11 +1467,10 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forc
   SynthInput pred{};
   pred.nsrc = (int)pi.size();
   for (int i = 0; i < pred.nsrc; ++i) {
-    pred.src[i] = (const double2*)hist + (int64_t)i * ctx->state_count;
+    pred.src[i] = hist + (int64_t)i * ctx->state_count;
     pred.coef[i] = pi[i];
   }
   pred.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
-  double2* hb = (double2*)hist_bar;
   SynthInput in = pred;
   in.adj = hb;  // hbar_out[0]; n_bar is formed inside the five-field synthesis
   in.adj_step = 1;
@@ -1480,6 +1482,150 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forc
     NSE_HIP(ctx, launch_ring_adjoint(v, g.plan, ctx->stream));
     NSE_HIP(ctx, launch_synthesis_adjoint(v, ctx->stream));
     NSE_HIP(ctx, launch_prep_step_adjoint(v, st, pred, hb, ctx->stream));
+  }
+  return NSE_OK;
+}
+
+// Runs `enqueue` (the steps i0 .. i1 - 1 of a trajectory sequence) from a
+// captured graph kept under (kind, traj, aux, forcing, n, i0, i1); captured on
+// the context's private stream (the context stream may be the null stream).
+template <typename F>
+nse_status run_sequence_graph(nse_ctx* ctx, int kind, const void* traj, const void* aux,
+                                     const void* forcing, int64_t n, int64_t i0, int64_t i1,
+                                     F&& enqueue) {
+  for (auto& g : ctx->graphs) {
+    if (g.kind == kind && g.hist == traj && g.aux == aux && g.forcing == forcing && g.n == n &&
+        g.i0 == i0 && g.i1 == i1) {
+      g.used = ++ctx->graph_clock;
+      NSE_HIP(ctx, hipGraphLaunch(g.exec, ctx->stream));
+      return NSE_OK;
+    }
+  }
+  if (ctx->graphs.size() >= kGraphCache) {
+    auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+    NSE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    destroy_graph(*lru);
+    ctx->graphs.erase(lru);
+  }
+  if (!ctx->cap_stream)
+    NSE_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  GraphEntry ge;
+  ge.kind = kind;
+  ge.hist = traj;
+  ge.aux = aux;
+  ge.forcing = forcing;
+  ge.n = n;
+  ge.i0 = i0;
+  ge.i1 = i1;
+  const hipStream_t user_stream = ctx->stream;
+  ctx->stream = ctx->cap_stream;
+  nse_status s = NSE_OK;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = enqueue();
+    e = hipStreamEndCapture(ctx->stream, &gr);
+  }
+  ctx->stream = user_stream;
+  if (s != NSE_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "graph capture of a trajectory sequence");
+  ge.graph = gr;
+  e = hipGraphInstantiate(&ge.exec, gr, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    return hip_fail(ctx, e, "hipGraphInstantiate");
+  }
+  ge.used = ++ctx->graph_clock;
+  ctx->graphs.push_back(ge);
+  NSE_HIP(ctx, hipGraphLaunch(ge.exec, ctx->stream));
+  return NSE_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forcing, int64_t step,
+                            double* hist_bar) {
+  if (!ctx) return NSE_ERR_ARG;
+  (void)forcing;  // the forcing enters affinely and is not differentiated
+  if (!hist || !hist_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  if (hist == hist_bar) return fail(ctx, NSE_ERR_ARG, "hist and hist_bar may not alias");
+  if (step < 0) return fail(ctx, NSE_ERR_ARG, "step must be >= 0");
+  if (ctx->params.newton_iters != 1)
+    return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
+  nse_status s = ensure_adjoint_buffers(ctx);
+  if (s != NSE_OK) return s;
+  return enqueue_step_adjoint(ctx, (const double2*)hist, step, (double2*)hist_bar);
+}
+
+nse_status nse_step_trajectory(nse_ctx* ctx, double* traj, const double* forcing, int64_t step0,
+                               int32_t nsteps) {
+  if (!ctx) return NSE_ERR_ARG;
+  if (!traj) return fail(ctx, NSE_ERR_ARG, "traj must be non-NULL");
+  if (step0 < 0) return fail(ctx, NSE_ERR_ARG, "step0 must be >= 0");
+  if (nsteps < 0) return fail(ctx, NSE_ERR_ARG, "nsteps must be >= 0");
+  const int64_t S = ctx->state_count, n = nsteps;
+  double2* tr = (double2*)traj;
+  const double2* f = (const double2*)forcing;
+  const int p = ctx->params.order;
+  // step i reads the history at traj[n - i] and writes traj[n - i - 1]
+  int64_t i = 0;
+  for (; i < n && step0 + i <= p; ++i) {
+    nse_status s = enqueue_step(ctx, tr + (n - i) * S, f, step0 + i, true);
+    if (s != NSE_OK) return s;
+  }
+  if (i == n) return NSE_OK;
+  const bool graph =
+      (ctx->params.flags & NSE_FLAG_GRAPH) && !ctx->profiling && n - i >= 2;
+  const int64_t i0 = i;
+  const auto body = [&]() -> nse_status {
+    for (int64_t j = i0; j < n; ++j) {
+      nse_status s = enqueue_step(ctx, tr + (n - j) * S, f, step0 + j, true);
+      if (s != NSE_OK) return s;
+    }
+    return NSE_OK;
+  };
+  if (!graph) return body();
+  return run_sequence_graph(ctx, 1, traj, nullptr, forcing, n, i0, n, body);
+}
+
+nse_status nse_step_adjoint_trajectory(nse_ctx* ctx, const double* traj, const double* forcing,
+                                       int64_t step0, int32_t nsteps, double* hist_bar) {
+  if (!ctx) return NSE_ERR_ARG;
+  (void)forcing;  // the forcing enters affinely and is not differentiated
+  if (!traj || !hist_bar) return fail(ctx, NSE_ERR_ARG, "NULL array");
+  if (step0 < 0) return fail(ctx, NSE_ERR_ARG, "step0 must be >= 0");
+  if (nsteps < 0) return fail(ctx, NSE_ERR_ARG, "nsteps must be >= 0");
+  if (ctx->params.newton_iters != 1)
+    return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
+  const int64_t S = ctx->state_count, n = nsteps;
+  const double2* tr = (const double2*)traj;
+  double2* hb = (double2*)hist_bar;
+  if (hb + (ctx->params.order + 1) * S > tr && tr + (n + ctx->params.order + 1) * S > hb)
+    return fail(ctx, NSE_ERR_ARG, "hist_bar may not overlap traj");
+  nse_status s = ensure_adjoint_buffers(ctx);
+  if (s != NSE_OK) return s;
+  const int p = ctx->params.order;
+  // steps n - 1 .. 0; those with fixed coefficients (step0 + i > p) first
+  const int64_t ifix = std::max<int64_t>(0, std::min<int64_t>(n, p + 1 - step0));
+  const auto body = [&]() -> nse_status {
+    for (int64_t i = n - 1; i >= ifix; --i) {
+      nse_status st = enqueue_step_adjoint(ctx, tr + (n - i) * S, step0 + i, hb);
+      if (st != NSE_OK) return st;
+    }
+    return NSE_OK;
+  };
+  const bool graph =
+      (ctx->params.flags & NSE_FLAG_GRAPH) && !ctx->profiling && n - ifix >= 2;
+  s = graph ? run_sequence_graph(ctx, 2, traj, hist_bar, forcing, n, ifix, n, body) : body();
+  if (s != NSE_OK) return s;
+  for (int64_t i = ifix - 1; i >= 0; --i) {
+    s = enqueue_step_adjoint(ctx, tr + (n - i) * S, step0 + i, hb);
+    if (s != NSE_OK) return s;
   }
   return NSE_OK;
 }

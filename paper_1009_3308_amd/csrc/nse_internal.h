@@ -138,6 +138,8 @@ struct AnalOutput {
   const double2* forcing;    // may be null
   double2* iter;             // ANAL_STEP_ITER output
   int* nonfinite;            // may be null
+  int shift;                 // ANAL_STEP_FINAL on a trajectory buffer: the new state goes
+                             // to hist[-1] (the slot before the history), nothing rotates
   // ANAL_NDF (k_analysis_otf): the corrector sweep of a device-controlled
   // adaptive run in the epilogue, with h, the order and the forcing scale from
   // the control block: d = (h (s f - n) - h nu lambda y0 - psi) / (alpha_k + h nu lambda),

@@ -230,6 +230,10 @@ __device__ inline void finish_degree_from(const GroupView& g, const AnalOutput& 
     out.iter[slot] = a;
     return;
   }
+  if (out.shift) {
+    out.hist[slot - out.state_count] = a;
+    return;
+  }
 #pragma unroll
   for (int j = kMaxStepCoef - 1; j >= 1; --j)
     if (j < nold) out.hist[(int64_t)j * out.state_count + slot] = old[j - 1];

@@ -162,6 +162,58 @@ def test_step_adjoint_needs_one_sweep():
     s.close()
 
 
+@pytest.mark.parametrize("order,step0,n,graph", [(2, 0, 13, True), (2, 5, 20, True),
+                                                 (3, 1, 9, False), (1, 0, 4, True)])
+def test_step_trajectory_equals_nse_step(order, step0, n, graph):
+    """The trajectory buffer holds, slot by slot, the histories of step-by-step
+    nse_step calls (the same kernels; bitwise), start-up steps and graph
+    replay included; its adjoint equals the per-step adjoint loop."""
+    N, nu = 31, 1e-3
+    _say(f"case: trajectory buffer p={order} step0={step0} n={n} graph={graph}")
+    s = pkg.Sphere([(N, 0, nu)], omega=OMEGA, dt=1e-3, order=order, graph=graph,
+                   stream=torch.cuda.current_stream())
+    f = pkg.to_device(I.forcing(N))
+    h = s.new_history()
+    for j in range(order + 1):
+        h[j] = pkg.to_device(I.member_state(j, N))
+    tr = s.new_trajectory(n)
+    tr[n:] = h
+    s.step_trajectory(tr, f, step0, n)
+    seg = []
+    for i in range(n):
+        seg.append(h.clone())
+        assert torch.equal(tr[n - i:n - i + order + 1], h), i
+        s.step(h, f, step0 + i, 1)
+    assert torch.equal(tr[0:order + 1], h)
+    hb_ref = s.new_history()
+    for j in range(order + 1):
+        hb_ref[j] = pkg.to_device(I.cotangent(N, 20 + j))
+    hb = hb_ref.clone()
+    for i in reversed(range(n)):
+        s.step_adjoint(seg[i], f, step0 + i, hb_ref)
+    s.step_adjoint_trajectory(tr, f, step0, n, hb)
+    assert torch.equal(hb, hb_ref)
+    s.step_adjoint_trajectory(tr, f, step0, n, hb)  # replay of the cached graph
+    hb2 = hb_ref.clone()
+    for i in reversed(range(n)):
+        s.step_adjoint(seg[i], f, step0 + i, hb2)
+    assert torch.equal(hb, hb2)
+    s.close()
+
+
+def test_step_trajectory_argument_errors():
+    s = pkg.Sphere([(15, 0, 1e-3)], omega=OMEGA, dt=1e-3)
+    tr = s.new_trajectory(4)
+    for step0, n in ((-1, 4), (0, -1)):
+        assert pkg.lib().nse_step_trajectory(s._handle(), tr.data_ptr(), None, step0,
+                                             n) == pkg.NSE_ERR_ARG
+    assert pkg.lib().nse_step_trajectory(s._handle(), None, None, 0, 4) == pkg.NSE_ERR_ARG
+    st = pkg.lib().nse_step_adjoint_trajectory(s._handle(), tr.data_ptr(), None, 0, 4,
+                                               tr[2:].data_ptr())  # hist_bar inside traj
+    assert st == pkg.NSE_ERR_ARG
+    s.close()
+
+
 def _gpu_loss(alpha, target, N):
     w = torch.where(torch.as_tensor(I.degrees_orders(N)[1], device=alpha.device) > 0, 2.0, 1.0)
     d = alpha - target
