@@ -37,12 +37,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_SOURCES = {
     "synthesis": ["paper_1009_3308_amd/csrc/synthesis.hip",
                   "paper_1009_3308_amd/csrc/spectral_ops.h",
+                  "paper_1009_3308_amd/csrc/ndf_control.h",
                   "paper_1009_3308_amd/csrc/nse_internal.h"],
     "ring": ["paper_1009_3308_amd/csrc/ring_fft.hip",
              "paper_1009_3308_amd/csrc/nse_internal.h"],
     "analysis": ["paper_1009_3308_amd/csrc/analysis.hip",
                  "paper_1009_3308_amd/csrc/lane_ops.h",
                  "paper_1009_3308_amd/csrc/spectral_ops.h",
+                 "paper_1009_3308_amd/csrc/ndf_control.h",
                  "paper_1009_3308_amd/csrc/nse_internal.h"],
 }
 
@@ -503,6 +505,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-example2", action="store_true")
+    ap.add_argument("--example2-t", type=float, default=60.0,
+                    help="end time of the Example 2 adaptive run (the paper's: 60)")
     ap.add_argument("--ensemble-group-only", action="store_true",
                     help="replace the mixed-truncation ensemble leg by its N=255 group alone "
                          "(16 members in one context, one truncation group, no forked streams)")
@@ -622,8 +626,8 @@ def main():
         log(f"bench: adjoint {adj}")
 
     if not args.no_example2:
-        log("bench: Example 2 adaptive run, N=100, t = 0..60")
-        ex2 = example2_timing(pkg, torch)
+        log(f"bench: Example 2 adaptive run, N=100, t = 0..{args.example2_t:g}")
+        ex2 = example2_timing(pkg, torch, T=args.example2_t)
         extra["example2_adaptive"] = ex2
         log(f"bench: example 2 {ex2}")
 
