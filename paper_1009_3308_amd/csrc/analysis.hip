@@ -48,7 +48,6 @@ constexpr int kOtfDeg = kButterfly;  // degrees per wave
 
 template <typename TT, int R, bool NDF>
 __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
-  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   const int N = g.N, nh = g.nh;
   const int ntile = (N + 1 + 63) / 64;
   const int item = xcd_item(blockIdx.x, 4 * ntile);
@@ -121,6 +120,9 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
 #pragma unroll
     for (int i = 0; i < kDegreeInputs; ++i) pre[threadIdx.x * kDegreeInputs + i] = din[i];
   }
+  // an ended attempt of a device-controlled run: checked once the loads are in
+  // flight (nothing is stored before this barrier), so the flag costs no wait
+  if (gate_closed(g)) return;
   __syncthreads();
   if (!active) return;
   TT Wer[R], Wei[R], Wor[R], Woi[R];
@@ -161,6 +163,9 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     }
   }
   lane_butterfly16(sr, si, lane);
+  if constexpr (!NDF) {
+    if ((lane & 3) != 0) return;
+  }
   const int j = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) +
                 ((lane >> 2) & 1);
   const int k = kt + j0 + j;
@@ -178,7 +183,6 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       atomicMax(out.nrow + copy * kNdfSpreadStride + (lane >> 4), bits);
     }
   } else {
-    if ((lane & 3) != 0) return;
     if (k > N - m) return;
     finish_degree_from(g, out, b, m, k, (double)sr[0], (double)si[0],
                        pre + (k - kt) * kDegreeInputs);

@@ -527,7 +527,6 @@ __device__ __forceinline__ void wave_fft(double2* x, const double2* tw, int lane
 // fused pass, waves 0..2 the forward transforms.
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
-  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int M = 3 * S, PS = wave_row(S);
   const int N = g.N, nlat = g.nlat;
   const int lat = xcd_item(blockIdx.x, 8);
@@ -597,6 +596,9 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
     const int k = N + 1 + t - a * (M - 2 * N - 1);
     lds[(3 * a + k % 3) * PS + pad(k / 3)] = make_double2(0.0, 0.0);
   }
+  // an ended attempt of a device-controlled run: checked once the loads are in
+  // flight (nothing is stored before this barrier), so the flag costs no wait
+  if (gate_closed(g)) return;
   __syncthreads();
   if (wave < 6) wave_fft<S, 0, 1, 1, false>(lds + wave * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
   __syncthreads();
@@ -641,7 +643,6 @@ size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(
 template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode,
                                              double* grid_out) {
-  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int PTS = (MAXM + NT - 1) / NT;
   const int N = g.N, M = CM > 0 ? CM : g.M, nlat = g.nlat;
   const int lat = xcd_item(blockIdx.x, 8);
@@ -680,6 +681,9 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   // inverse transforms of f0 + i f1 and f2 + i f3, then the grid product
   load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + fstride, F0 + 2 * fstride, F0 + 3 * fstride, lat,
                       N, M, nlat);
+  // an ended attempt of a device-controlled run (only nonlinear-mode launches
+  // are gated): checked once the loads are in flight, nothing stored before
+  if (gate_closed(g)) return;
   __syncthreads();
   const double inv_sin2 = 1.0 / sin2;
   if constexpr (CM > 0) {

@@ -64,7 +64,6 @@ size_t synthesis_lds_bytes(int N, int NF) {
 template <typename TT, int NF, int R = 1>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthInput in,
                                                               int mode) {
-  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int kRed = 4 * NF;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
@@ -90,6 +89,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
     rcv[i] = (k >= 2 && k < L) ? g.rec_a[rec_slot(N, m + k, m)] : make_double2(0.0, 0.0);
   }
   load_order(a, g, in, b, m, L);
+  // an ended attempt of a device-controlled run: checked once the loads are in
+  // flight (nothing is stored before this barrier), so the flag costs no wait
+  if (gate_closed(g)) return;
   __syncthreads();
   build_panel<NF>(pan, a, N, m, L, mode, in.coriolis, in.stream != 0);
   if (NF == 5) {
@@ -261,7 +263,6 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 // latitudes per lane (R) and the cross-wave sums are those of k_synthesis.
 template <int R>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
-  if (gate_closed(g)) return;  // an ended attempt of a device-controlled run
   constexpr int kRed = 16;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
@@ -351,6 +352,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
     rc[k] = c;
     dc[k] = make_double2(e.x, (k < K) ? dl : 0.0);
   }
+  // an ended attempt of a device-controlled run: checked once the loads are in
+  // flight (nothing is stored before this barrier), so the flag costs no wait
+  if (gate_closed(g)) return;
   __syncthreads();
 
   // acc[r][4 f + 2 q + c]: field f, q = 0 even / 1 odd part, c = 0 re / 1 im
