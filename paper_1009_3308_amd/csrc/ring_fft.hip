@@ -632,6 +632,146 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   }
 }
 
+// Adjoint of the ring step on the same split transforms (M = 3 S; the
+// operation is that of k_ring_adj below): nine inverse S-point transforms
+// (rows 3a + k1: a = 0, 1 the forward pairs f0 + i f1 and f2 + i f3, a = 2 the
+// real field of spectrum Qbar / 2), one fused pass at n2 (inverse radix 3 of
+// the three arrays, the cotangents gbar at S n1 + n2, forward radix 3 of
+// gbar0 + i gbar1 and gbar2 + i gbar3), six forward S-point transforms into
+// rows 0..5, and the unpacking of the two real transforms of each array.
+// Waves take the rows in turn, so any NT >= max(S, 384) covers them.
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
+  constexpr int M = 3 * S, PS = wave_row(S), NW = NT / 64;
+  const int N = g.N, nlat = g.nlat;
+  const int lat = xcd_item(blockIdx.x, 8);
+  if (lat >= nlat) return;
+  const int b = blockIdx.y;
+  const int p = lat < g.nh ? lat : nlat - 1 - lat;
+  extern __shared__ double2 lds[];
+  double2* tw = lds + 9 * PS;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t fstride = (int64_t)(N + 1) * nlat;
+  const double2* F5 = g.Fa + (int64_t)b * 5 * fstride + lat;
+
+  // loads: thread t takes order m = t mod (N+1) of array a = t / (N+1) (both
+  // fields of a forward pair, or the fifth field for a = 2) and the twiddle
+  // half table, all requested before the first LDS write
+  constexpr int KT = (M / 2 + NT - 1) / NT;
+  constexpr int KI = (3 * (S + 1) + NT - 1) / NT;  // N + 1 <= S + 1
+  const int n1 = N + 1;
+  double2 tv[KT], ga[KI], gb[KI];
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) tv[i] = g.tw[j];
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    ga[i] = gb[i] = make_double2(0.0, 0.0);
+    if (idx < 3 * n1) {
+      const int a = idx >= 2 * n1 ? 2 : (idx >= n1 ? 1 : 0), m = idx - a * n1;
+      const double2* Fa = F5 + (int64_t)(2 * a) * fstride + (int64_t)m * nlat;
+      ga[i] = Fa[0];
+      if (a < 2) gb[i] = Fa[fstride];
+    }
+  }
+  const double x = g.mu[p];
+  const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
+  const double clat = (6.283185307179586477 / M) * g.w[p];
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (j < M / 2) tw[j] = tv[i];
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx < 3 * n1) {
+      const int a = idx >= 2 * n1 ? 2 : (idx >= n1 ? 1 : 0), m = idx - a * n1;
+      double2* rows = lds + 3 * a * PS;
+      const int k = M - m;
+      if (a < 2) {
+        if (m == 0) {
+          rows[0] = make_double2(ga[i].x, gb[i].x);
+        } else {
+          rows[(m % 3) * PS + pad(m / 3)] = make_double2(ga[i].x - gb[i].y, ga[i].y + gb[i].x);
+          rows[(k % 3) * PS + pad(k / 3)] = make_double2(ga[i].x + gb[i].y, gb[i].x - ga[i].y);
+        }
+      } else {
+        // x_0 = Re Qbar_0, x_m = Qbar_m / 2, x_{M-m} = conj(Qbar_m) / 2
+        if (m == 0) {
+          rows[0] = make_double2(ga[i].x, 0.0);
+        } else {
+          rows[(m % 3) * PS + pad(m / 3)] = make_double2(0.5 * ga[i].x, 0.5 * ga[i].y);
+          rows[(k % 3) * PS + pad(k / 3)] = make_double2(0.5 * ga[i].x, -0.5 * ga[i].y);
+        }
+      }
+    }
+  }
+  // the zero band N < k < M - N of the three arrays
+  const int zb = M - 2 * N - 1;
+  for (int t = threadIdx.x; t < 3 * zb; t += NT) {
+    const int a = t >= 2 * zb ? 2 : (t >= zb ? 1 : 0);
+    const int k = N + 1 + t - a * zb;
+    lds[(3 * a + k % 3) * PS + pad(k / 3)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int r = wave; r < 9; r += NW)
+    wave_fft<S, 0, 1, 1, false>(lds + r * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
+  __syncthreads();
+  // fused pass at n2 = threadIdx.x: the grid values at S n1 + n2 of the three
+  // arrays, gbar0 + i gbar1 = qb (g2, -g3) and gbar2 + i gbar3 = qb (g0, -g1)
+  // with qb = c_lat qbar / s^2, and the forward radix 3 and twiddles of both
+  for (int n2 = threadIdx.x; n2 < S; n2 += NT) {
+    const double2 w1 = tw_full<M>(tw, n2), w2 = tw_full<M>(tw, 2 * n2);
+    double2 y[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) y[a][k1] = lds[(3 * a + k1) * PS + pad(n2)];
+      y[a][1] = cmul(y[a][1], make_double2(w1.x, -w1.y));
+      y[a][2] = cmul(y[a][2], make_double2(w2.x, -w2.y));
+      butterfly<3>(y[a], 1.0);
+    }
+    double2 z[2][3];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+      const double qb = clat * y[2][n1].x * inv_sin2;
+      z[0][n1] = make_double2(qb * y[1][n1].x, -qb * y[1][n1].y);
+      z[1][n1] = make_double2(qb * y[0][n1].x, -qb * y[0][n1].y);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      butterfly<3>(z[a], -1.0);
+      z[a][1] = cmul(z[a][1], w1);
+      z[a][2] = cmul(z[a][2], w2);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) lds[(3 * a + k1) * PS + pad(n2)] = z[a][k1];
+    }
+  }
+  __syncthreads();
+  for (int r = wave; r < 6; r += NW)
+    wave_fft<S, 0, 1, -1, false>(lds + r * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
+  __syncthreads();
+  // unpack two real transforms per array, Z_k at row 3 a + k mod 3, k / 3:
+  // A_m = (Z_m + conj Z_{M-m}) / 2, B_m = (Z_m - conj Z_{M-m}) / (2 i); times 2 for m >= 1
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  for (int m = threadIdx.x; m <= N; m += NT) {
+    const double sc = (m == 0) ? 0.5 : 1.0;
+    const int mc = m == 0 ? 0 : M - m;
+#pragma unroll
+    for (int arr = 0; arr < 2; ++arr) {
+      const double2 zm = lds[(3 * arr + m % 3) * PS + pad(m / 3)];
+      const double2 zc = lds[(3 * arr + mc % 3) * PS + pad(mc / 3)];
+      Fb[(int64_t)(2 * arr) * fstride + m] = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
+      Fb[(int64_t)(2 * arr + 1) * fstride + m] = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
+    }
+  }
+}
+
 }  // namespace
 
 size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(M) + M / 2); }
@@ -889,8 +1029,17 @@ hipError_t ring_dispatch(int M, F&& launch) {
   return launch(integral_constant<int, kMaxM>{}, integral_constant<int, 512>{}, integral_constant<int, 0>{});
 }
 
+// the split adjoint ring: nine rows of S + S/16 + 1 points and the twiddle half table
+size_t ring_adj_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(9 * wave_row(M / 3) + M / 2); }
+
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
+  if (g.M == 384 || g.M == 768) {
+    const size_t lds = ring_adj_nl_lds_bytes(g.M);
+    if (g.M == 384) hipLaunchKernelGGL((k_ring_adj_nl<128, 384>), grid, dim3(384), lds, s, g);
+    else hipLaunchKernelGGL((k_ring_adj_nl<256, 384>), grid, dim3(384), lds, s, g);
+    return hipGetLastError();
+  }
   const size_t lds = ring_lds_bytes(g.M);
   return ring_dispatch(g.M, [&](auto maxm, auto nt, auto cm) {
     constexpr int MAXM = decltype(maxm)::value, NT = decltype(nt)::value, CM = decltype(cm)::value;
