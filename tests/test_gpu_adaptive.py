@@ -57,9 +57,9 @@ def _compare_logs(glog, olog, label, stops=()):
             assert abs(gerr - oerr) <= 1e-7 * oerr + 1e-300, (label, i, g, o)
 
 
-def _oracle_integrator(N, nus, forcing, omega=OMEGA, **kw):
+def _oracle_integrator(N, nus, forcing, omega=OMEGA, nlat=None, **kw):
     """One system of len(nus) members of truncation N (states concatenated)."""
-    S = O.Sphere(N)
+    S = O.Sphere(N, nlat)
     P = O.coeff_count(N)
     L = torch.cat([(nu * S.lam).to(torch.float64) for nu in nus])
 
@@ -105,6 +105,32 @@ def test_adaptive_matches_oracle(N, nu, T, rtol, max_newton):
     # no callback: the controller ran on the device, the host waited once for
     # F(t0) and once per batch of attempts
     assert stats["waits"] <= 2 + len(glog) // 4, stats
+
+
+def test_adaptive_wide_grid_matches_oracle():
+    """The device-controlled sweeps on a grid of more than 192 northern
+    latitudes, where each analysis wave takes two blocks of 16 degrees (one
+    recurrence, two lane reductions, the corrector and the norm maxima of both)."""
+    N, nlat, nu, T = 140, 400, 1e-3, 0.3
+    _say(f"case adaptive N={N} nlat={nlat} T={T}")
+    a0 = I.initial_state(N)
+    f = I.forcing(N)
+    s = pkg.Sphere([(N, nlat, nu)], omega=OMEGA, dt=1e-3, order=2)
+    s.adaptive_begin(pkg.to_device(a0), 0.0, rtol=1e-4, atol=1e-6, forcing=pkg.to_device(f))
+    out, stats = s.adaptive_advance(T)
+    glog = s.adaptive_log()
+    g = out.cpu()
+    s.close()
+    ft = O.to_tensor(f)
+    integ = _oracle_integrator(N, [nu], lambda t: ft, nlat=nlat, rtol=1e-4, atol=1e-6)
+    integ.begin(O.to_tensor(a0), 0.0)
+    o = integ.advance(T)
+    _compare_logs(glog, integ.log, f"N={N} nlat={nlat}", (T,))
+    scale = float(o.abs().max())
+    diff = float((g - o).abs().max())
+    _say(f"  attempts {len(glog)} state diff {diff / scale:.3e}")
+    assert stats["t"] == T
+    assert diff <= 1e-10 * scale
 
 
 def test_adaptive_stops_and_time_dependent_forcing():
