@@ -15,18 +15,22 @@
 // then either stored as the next fixed-point iterate or written to hist[0]
 // after rotating hist[j] <- hist[j-1].
 //
-// Workgroups of four waves per (order m, tile of 64 degrees, member). Orders
+// Workgroups of three waves per (order m, tile of 48 degrees, member). Orders
 // are taken in XCD-local chunks of four neighbouring m. The ring spectra
 // W[m][lat] of an order are contiguous, so the fold's loads are coalesced; the
-// step update's inputs (forcing, history) of the tile's 64 degrees are
+// step update's inputs (forcing, history) of the tile's 48 degrees are
 // requested with them and wait in LDS, so the epilogue issues no load.
+// Three waves per workgroup balance the CUs best: the waves of a launch are
+// dealt out a workgroup at a time, and with four (or two) waves the most
+// loaded CUs held a larger share of them (T511: 27.0 us against 30.9 and 28.1).
 #include "lane_ops.h"
 #include "spectral_ops.h"
 
 namespace nse {
 
-constexpr int kAnalWaves = 4;
+constexpr int kAnalWaves = 3;
 constexpr int kAnalThreads = 64 * kAnalWaves;
+constexpr int kAnalTile = kAnalWaves * kButterfly;  // degrees per workgroup
 // The Legendre values are continued in registers (OTF) rather than streamed
 // from a table. Wave w owns the degrees 16 w .. 16 w + 15 of the tile and its lanes are
 // latitudes, lane l taking p = l + 64 r for r < R (R = ceil(nh / 64)). Each lane
@@ -49,18 +53,19 @@ constexpr int kOtfDeg = kButterfly;  // degrees per wave
 template <typename TT, int R, bool NDF>
 __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
   const int N = g.N, nh = g.nh;
-  const int ntile = (N + 1 + 63) / 64;
+  const int ntile = (N + 1 + kAnalTile - 1) / kAnalTile;
   const int item = xcd_item(blockIdx.x, 4 * ntile);
   const int m = item / ntile;
   const int tile = item - m * ntile;
-  if (m > N || tile * 64 > N - m) return;  // uniform across the workgroup
+  if (m > N || tile * kAnalTile > N - m) return;  // uniform across the workgroup
   const int b = blockIdx.y;
-  extern __shared__ double2 wsh[];  // We [nh], Wo [nh], rc [64], step inputs [64][kDegreeInputs]
+  // We [nh], Wo [nh], rc [kAnalTile], step inputs [kAnalTile][kDegreeInputs]
+  extern __shared__ double2 wsh[];
   double2* rc = wsh + 2 * nh;
-  double2* pre = rc + 64;
+  double2* pre = rc + kAnalTile;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int kt = tile * 64;  // first degree offset k = l - m of the tile
+  const int kt = tile * kAnalTile;  // first degree offset k = l - m of the tile
 
   const int j0 = wave * kOtfDeg;        // the wave's first degree within the tile
   const bool active = kt + j0 <= N - m;  // some degree of this wave is analysed
@@ -82,14 +87,14 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
     }
   }
   // fold the ring spectra of each latitude pair: We = Q(p) + Q(p'), Wo = Q(p) - Q(p');
-  // all of the thread's pairs (p = t and t + 256; nh <= kMaxM / 4 = 384) are
-  // requested before the coefficient pairs are computed, so that their square
-  // roots and the LDS writes wait for one memory round trip
-  static_assert(kMaxM / 4 <= 2 * kAnalThreads, "two ring pairs per thread");
+  // all of the thread's pairs (p = t + i kAnalThreads; nh <= kMaxM / 4 = 384)
+  // are requested before the coefficient pairs are computed, so that their
+  // square roots and the LDS writes wait for one memory round trip
+  constexpr int kFold = (kMaxM / 4 + kAnalThreads - 1) / kAnalThreads;  // pairs per thread
   const double2* Wb = g.W + ((int64_t)b * (N + 1) + m) * g.nlat;
-  double2 qn[2], qs[2];
+  double2 qn[kFold], qs[kFold];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kFold; ++i) {
     const int p = threadIdx.x + i * kAnalThreads;
     qn[i] = qs[i] = make_double2(0.0, 0.0);
     if (p < nh) {
@@ -97,19 +102,19 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
       qs[i] = Wb[g.nlat - 1 - p];
     }
   }
-  // the step update's inputs of degree kt + t (wave 0), kept until the epilogue
+  // the step update's inputs of degree kt + t (t < kAnalTile), kept until the epilogue
   double2 din[kDegreeInputs];
-  const bool dthread = threadIdx.x < 64 && kt + (int)threadIdx.x <= N - m;
+  const bool dthread = (int)threadIdx.x < kAnalTile && kt + (int)threadIdx.x <= N - m;
   if (dthread) load_degree_inputs(g, out, b, m, kt + threadIdx.x, din);
   // recurrence pairs of the tile's degrees (k >= 2 of the order, from the
   // group's coefficient table; zero past degree N+1, whose values are not used)
-  if (threadIdx.x < 64) {
+  if ((int)threadIdx.x < kAnalTile) {
     const int k = kt + threadIdx.x;
     rc[threadIdx.x] = (k >= 2 && k <= N + 1 - m) ? g.rec_a[rec_slot(N, m + k, m)]
                                                  : make_double2(0.0, 0.0);
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kFold; ++i) {
     const int p = threadIdx.x + i * kAnalThreads;
     if (p < nh) {
       wsh[p] = make_double2(qn[i].x + qs[i].x, qn[i].y + qs[i].y);
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
 }  // namespace
 
 size_t analysis_otf_lds_bytes(int nh) {
-  return sizeof(double2) * (size_t)(2 * nh + 64 + 64 * kDegreeInputs);
+  return sizeof(double2) * (size_t)(2 * nh + kAnalTile * (1 + kDegreeInputs));
 }
 
 template <typename TT, bool NDF>
@@ -211,7 +216,7 @@ hipError_t launch_analysis_otf(dim3 grid, dim3 block, size_t lds, hipStream_t s,
 
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s) {
   dim3 block(kAnalThreads);
-  const int ntile = (g.N + 1 + 63) / 64;
+  const int ntile = (g.N + 1 + kAnalTile - 1) / kAnalTile;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
   const size_t lds = analysis_otf_lds_bytes(g.nh);
   const bool ndf = out.mode == ANAL_NDF;
