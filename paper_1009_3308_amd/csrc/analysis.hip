@@ -15,22 +15,24 @@
 // then either stored as the next fixed-point iterate or written to hist[0]
 // after rotating hist[j] <- hist[j-1].
 //
-// Workgroups of three waves per (order m, tile of 48 degrees, member). Orders
+// Workgroups of NW waves per (order m, tile of 16 NW degrees, member). Orders
 // are taken in XCD-local chunks of four neighbouring m. The ring spectra
 // W[m][lat] of an order are contiguous, so the fold's loads are coalesced; the
-// step update's inputs (forcing, history) of the tile's 48 degrees are
-// requested with them and wait in LDS, so the epilogue issues no load.
-// Three waves per workgroup balance the CUs best: the waves of a launch are
-// dealt out a workgroup at a time, and with four (or two) waves the most
-// loaded CUs held a larger share of them (T511: 27.0 us against 30.9 and 28.1).
+// step update's inputs (forcing, history) of the tile's degrees are requested
+// with them and wait in LDS, so the epilogue issues no load.
+// With three or more latitudes per lane three waves per workgroup balance the
+// CUs best: the waves of a launch are dealt out a workgroup at a time, and with
+// four (or two) waves the most loaded CUs held a larger share of them (T511:
+// 27.0 us against 30.9 and 28.1). With fewer latitudes per lane (N = 100 on
+// 160 x 320) four waves are faster (4.7 against 5.0 us; 4.8 against 5.9 us with
+// the corrector sweep of a device-controlled run).
 #include "lane_ops.h"
 #include "spectral_ops.h"
 
 namespace nse {
 
-constexpr int kAnalWaves = 3;
-constexpr int kAnalThreads = 64 * kAnalWaves;
-constexpr int kAnalTile = kAnalWaves * kButterfly;  // degrees per workgroup
+// waves per workgroup for R latitudes per lane
+__host__ __device__ constexpr int anal_waves(int R) { return R >= 3 ? 3 : 4; }
 // The Legendre values are continued in registers (OTF) rather than streamed
 // from a table. Wave w owns the degrees 16 w .. 16 w + 15 of the tile and its lanes are
 // latitudes, lane l taking p = l + 64 r for r < R (R = ceil(nh / 64)). Each lane
@@ -51,7 +53,10 @@ namespace {
 constexpr int kOtfDeg = kButterfly;  // degrees per wave
 
 template <typename TT, int R, bool NDF>
-__global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, AnalOutput out) {
+__global__ __launch_bounds__(64 * anal_waves(R)) void k_analysis_otf(GroupView g, AnalOutput out) {
+  constexpr int kAnalWaves = anal_waves(R);
+  constexpr int kAnalThreads = 64 * kAnalWaves;
+  constexpr int kAnalTile = kAnalWaves * kButterfly;  // degrees per workgroup
   const int N = g.N, nh = g.nh;
   const int ntile = (N + 1 + kAnalTile - 1) / kAnalTile;
   const int item = xcd_item(blockIdx.x, 4 * ntile);
@@ -197,7 +202,8 @@ __global__ __launch_bounds__(kAnalThreads) void k_analysis_otf(GroupView g, Anal
 }  // namespace
 
 size_t analysis_otf_lds_bytes(int nh) {
-  return sizeof(double2) * (size_t)(2 * nh + kAnalTile * (1 + kDegreeInputs));
+  const int tile = anal_waves((nh + 63) / 64) * kButterfly;
+  return sizeof(double2) * (size_t)(2 * nh + tile * (1 + kDegreeInputs));
 }
 
 template <typename TT, bool NDF>
@@ -215,8 +221,10 @@ hipError_t launch_analysis_otf(dim3 grid, dim3 block, size_t lds, hipStream_t s,
 }
 
 hipError_t launch_analysis(const GroupView& g, const AnalOutput& out, hipStream_t s) {
-  dim3 block(kAnalThreads);
-  const int ntile = (g.N + 1 + kAnalTile - 1) / kAnalTile;
+  const int nw = anal_waves((g.nh + 63) / 64);
+  dim3 block(64 * nw);
+  const int tile = nw * kButterfly;
+  const int ntile = (g.N + 1 + tile - 1) / tile;
   dim3 grid(xcd_grid((g.N + 1) * ntile, 4 * ntile), g.nb);
   const size_t lds = analysis_otf_lds_bytes(g.nh);
   const bool ndf = out.mode == ANAL_NDF;
