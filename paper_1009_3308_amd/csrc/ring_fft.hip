@@ -213,12 +213,45 @@ template <> struct CtPlan<1536> { static constexpr int n = 4; static constexpr i
 
 constexpr int ct_log2(int x) { return x <= 1 ? 0 : 1 + ct_log2(x / 2); }
 
+// exp(SGN 2 pi i e / M) for 0 <= e < M from the half table tw[0 .. M/2) of
+// exp(-2 pi i e / M).
+template <int M, int SGN>
+__device__ __forceinline__ double2 tw_at(const double2* tw, int e) {
+  constexpr int half = M / 2;
+  double2 w = tw[e < half ? e : e - half];
+  if (e >= half) w = make_double2(-w.x, -w.y);
+  if (SGN > 0) w.y = -w.y;
+  return w;
+}
+
+// The twiddles w[r] = exp(SGN 2 pi i r e / M), r = 1 .. R-1, of one butterfly
+// (R e < R M / R = M): radix 4 and 8 read w, w^2 (and w^4) from the table and
+// form the other powers by products (at most two roundings more than a table
+// entry), which takes three of the seven table reads of a radix-8 butterfly.
+template <int R, int M, int SGN>
+__device__ __forceinline__ void stage_twiddles(double2* w, const double2* tw, int e) {
+  if constexpr (R == 4 || R == 8) {
+    w[1] = tw_at<M, SGN>(tw, e);
+    w[2] = tw_at<M, SGN>(tw, 2 * e);
+    w[3] = cmul(w[1], w[2]);
+    if constexpr (R == 8) {
+      w[4] = tw_at<M, SGN>(tw, 4 * e);
+      w[5] = cmul(w[1], w[4]);
+      w[6] = cmul(w[2], w[4]);
+      w[7] = cmul(w[3], w[4]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = tw_at<M, SGN>(tw, r * e);
+  }
+}
+
 // One Stockham stage of radix R at stride NS (a power of two) on NA arrays of
 // length M (x1 = x0 + padded_len(M) when NA = 2); SGN = -1 forward, +1 inverse.
 template <int R, int NS, int M, int NA, int NT, int SGN>
 __device__ __forceinline__ void stage_ct(double2* x0, const double2* tw) {
   constexpr int span = M / R, total = span * NA, MAXB = (total + NT - 1) / NT;
-  constexpr int step = M / (NS * R), half = M / 2, lg = ct_log2(NS);
+  constexpr int step = M / (NS * R), lg = ct_log2(NS);
   constexpr int PL = M + (M >> 4) + 1;
   double2 v[MAXB][R];
   int dst[MAXB];
@@ -234,15 +267,10 @@ __device__ __forceinline__ void stage_ct(double2* x0, const double2* tw) {
       for (int r = 0; r < R; ++r) v[c][r] = x[pad(j + r * span)];
       const int k = j & (NS - 1), q = j >> lg;
       if constexpr (NS > 1) {
-        const int ks = k * step;
+        double2 w[R];
+        stage_twiddles<R, M, SGN>(w, tw, k * step);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const int e = r * ks;  // < M
-          double2 w = tw[e < half ? e : e - half];
-          if (e >= half) w = make_double2(-w.x, -w.y);
-          if (SGN > 0) w.y = -w.y;  // the table holds exp(-2 pi i e / M)
-          v[c][r] = cmul(v[c][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], w[r]);
       }
       butterfly<R>(v[c], (double)SGN);
       dst[c] = a * PL + q * NS * R + k;
@@ -287,24 +315,20 @@ __device__ __forceinline__ void fft_ct_inverse_product(double2* x0, const double
     fft_ct_inverse_product<M, S + 1, NS * R, NT>(x0, tw, inv_sin2);
   } else {
     static_assert(CtPlan<M>::r[n - 1] == 3 && NS * 3 == M, "last stage: radix 3 at stride M/3");
-    constexpr int PL = M + (M >> 4) + 1, MAXB = (NS + NT - 1) / NT, half = M / 2;
+    constexpr int PL = M + (M >> 4) + 1, MAXB = (NS + NT - 1) / NT;
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
       const int j = threadIdx.x + b * NT;  // butterfly j (q = 0, k = j at stride NS = M/3)
       if (NS % NT == 0 || j < NS) {
         double2 v[2][3];
+        const double2 w1 = tw_at<M, 1>(tw, j);  // inverse twiddles of butterfly j
+        const double2 w2 = cmul(w1, w1);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
 #pragma unroll
           for (int r = 0; r < 3; ++r) v[a][r] = x0[a * PL + pad(j + r * NS)];
-#pragma unroll
-          for (int r = 1; r < 3; ++r) {
-            const int e = r * j;  // < M
-            double2 w = tw[e < half ? e : e - half];
-            if (e >= half) w = make_double2(-w.x, -w.y);
-            w.y = -w.y;  // inverse: the table holds exp(-2 pi i e / M)
-            v[a][r] = cmul(v[a][r], w);
-          }
+          v[a][1] = cmul(v[a][1], w1);
+          v[a][2] = cmul(v[a][2], w2);
           butterfly<3>(v[a], 1.0);
         }
 #pragma unroll
@@ -333,20 +357,16 @@ __device__ __forceinline__ void fft_ct_forward_store(double2* x0, const double2*
     fft_ct_forward_store<M, S + 1, NS * R, NT>(x0, tw, c, out, ostride, N);
   } else {
     static_assert(CtPlan<M>::r[n - 1] == 3 && NS * 3 == M, "last stage: radix 3 at stride M/3");
-    constexpr int MAXB = (NS + NT - 1) / NT, step = 1, half = M / 2;
+    constexpr int MAXB = (NS + NT - 1) / NT;
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
       const int j = threadIdx.x + b * NT;  // butterfly j = k (q = 0 at stride NS = M/3)
       if (j <= N) {
         double2 v0 = x0[pad(j)], v1 = x0[pad(j + NS)], v2 = x0[pad(j + 2 * NS)];
         if (j != 0) {
-          const int e1 = j * step, e2 = 2 * j * step;  // < M
-          double2 w1 = tw[e1 < half ? e1 : e1 - half];
-          if (e1 >= half) w1 = make_double2(-w1.x, -w1.y);
-          double2 w2 = tw[e2 < half ? e2 : e2 - half];
-          if (e2 >= half) w2 = make_double2(-w2.x, -w2.y);
+          const double2 w1 = tw_at<M, -1>(tw, j);  // j < M / 3
           v1 = cmul(v1, w1);
-          v2 = cmul(v2, w2);
+          v2 = cmul(v2, cmul(w1, w1));
         }
         // first output of the radix-3 butterfly: v0 + (v1 + v2)
         const double2 t = cadd(v1, v2);
@@ -379,7 +399,7 @@ __device__ __forceinline__ void fft_any(double2* x0, double2* x1, const FftPlan&
 // (one memory round trip for the ring instead of one per array); thread t
 // loads order m = t mod (N+1) of pair t / (N+1). Since 3N + 2 <= M <= MAXM,
 // 2 (N+1) <= 2 (MAXM / 3 + 1) <= KI NT.
-template <int MAXM, int NT>
+template <int MAXM, int NT, bool COPYTW = true>
 __device__ void load_ring(double2* x0, double2* x1, double2* tw, const double2* __restrict__ gtw,
                           const double2* __restrict__ Fa0, const double2* __restrict__ Fb0,
                           const double2* __restrict__ Fa1, const double2* __restrict__ Fb1,
@@ -402,12 +422,12 @@ __device__ void load_ring(double2* x0, double2* x1, double2* tw, const double2* 
 #pragma unroll
   for (int i = 0; i < KT; ++i) {
     const int j = threadIdx.x + i * NT;
-    if (j < M / 2) t[i] = gtw[j];
+    if (COPYTW && j < M / 2) t[i] = gtw[j];
   }
 #pragma unroll
   for (int i = 0; i < KT; ++i) {
     const int j = threadIdx.x + i * NT;
-    if (j < M / 2) tw[j] = t[i];
+    if (COPYTW && j < M / 2) tw[j] = t[i];
   }
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
@@ -481,12 +501,11 @@ __device__ __forceinline__ void wave_stage(double2* x, const double2* tw, int la
       for (int r = 0; r < R; ++r) v[b][r] = x[pad(j + r * span)];
       const int k = j & (NS - 1), q = j >> lg;
       if constexpr (NS > 1) {
+        // length-S twiddles: those of length M = 3 S at three times the index
+        double2 w[R];
+        stage_twiddles<R, M, SGN>(w, tw, 3 * k * step);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          double2 w = tw_full<M>(tw, 3 * r * k * step);
-          if (SGN > 0) w.y = -w.y;
-          v[b][r] = cmul(v[b][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[r]);
       }
       butterfly<R>(v[b], (double)SGN);
       dst[b] = q * NS * R + k;
@@ -605,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   // fused pass at n2 = threadIdx.x: inverse twiddles and radix 3 of both pairs,
   // the grid product at S n1 + n2, forward radix 3 and twiddles
   for (int n2 = threadIdx.x; n2 < S; n2 += NT) {
-    const double2 w1 = tw_full<M>(tw, n2), w2 = tw_full<M>(tw, 2 * n2);
+    const double2 w1 = tw_full<M>(tw, n2), w2 = cmul(w1, w1);
     double2 y[2][3];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -726,7 +745,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
   // arrays, gbar0 + i gbar1 = qb (g2, -g3) and gbar2 + i gbar3 = qb (g0, -g1)
   // with qb = c_lat qbar / s^2, and the forward radix 3 and twiddles of both
   for (int n2 = threadIdx.x; n2 < S; n2 += NT) {
-    const double2 w1 = tw_full<M>(tw, n2), w2 = tw_full<M>(tw, 2 * n2);
+    const double2 w1 = tw_full<M>(tw, n2), w2 = cmul(w1, w1);
     double2 y[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -780,7 +799,9 @@ size_t ring_lds_bytes(int M) { return sizeof(double2) * (size_t)(2 * padded_len(
 // neighbouring latitudes so that the strided reads of F share L2 lines.
 // MAXM: the largest M of the size class this instance serves and NT its
 // workgroup size (register arrays are sized from both).
-template <int MAXM, int NT, int CM>
+// TWG: the stages read their twiddles from the global half table (L1-resident)
+// instead of an LDS copy, which leaves 2 padded_len(M) entries of LDS per ring.
+template <int MAXM, int NT, int CM, bool TWG = false>
 __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode,
                                              double* grid_out) {
   constexpr int PTS = (MAXM + NT - 1) / NT;
@@ -793,7 +814,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   extern __shared__ double2 lds[];
   double2* A0 = lds;
   double2* A1 = lds + PL;
-  double2* tw = lds + 2 * PL;
+  double2* twl = lds + 2 * PL;  // unused with TWG
+  const double2* tw = TWG ? g.tw : twl;
   const double x = g.mu[p];
   const double sin2 = (1.0 - x) * (1.0 + x);
   const int64_t fstride = (int64_t)(N + 1) * nlat;
@@ -802,8 +824,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   if (mode == SYNTH_GRID) {
     // u_theta = f0 / sin, u_phi = -f1 / sin, zeta = f2
     const double rs = 1.0 / sqrt(sin2);
-    load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + fstride, F0 + 2 * fstride, F0 + 2 * fstride,
-                        lat, N, M, nlat);
+    load_ring<MAXM, NT, !TWG>(A0, A1, twl, g.tw, F0, F0 + fstride, F0 + 2 * fstride,
+                              F0 + 2 * fstride, lat, N, M, nlat);
     __syncthreads();
     fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
     double* g0 = grid_out + ((int64_t)0 * nlat + lat) * M;
@@ -819,8 +841,8 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   }
 
   // inverse transforms of f0 + i f1 and f2 + i f3, then the grid product
-  load_ring<MAXM, NT>(A0, A1, tw, g.tw, F0, F0 + fstride, F0 + 2 * fstride, F0 + 3 * fstride, lat,
-                      N, M, nlat);
+  load_ring<MAXM, NT, !TWG>(A0, A1, twl, g.tw, F0, F0 + fstride, F0 + 2 * fstride,
+                            F0 + 3 * fstride, lat, N, M, nlat);
   // an ended attempt of a device-controlled run (only nonlinear-mode launches
   // are gated): checked once the loads are in flight, nothing stored before
   if (gate_closed(g)) return;
@@ -1065,10 +1087,19 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
                        hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
   // the split kernel for M = 384 and 768 (T127, T255: ring 10.0 -> 9.4 us at
-  // T255). At M = 1536 the radix-8/8/8/3 plan over 1024 threads stays (21.8 us
-  // at T511): three one-wave 512-point transforms took 23.6 us, six 256-point
-  // ones with a radix-6 fused pass 26.8 us (twelve waves) and 25.8 us (six
-  // waves of two rows each, 52.7 KB of LDS: still two rings per CU)
+  // T255). At M = 1536 the radix-8/8/8/3 plan stays: three one-wave 512-point
+  // transforms took 23.6 us, six 256-point ones with a radix-6 fused pass 26.8
+  // us (twelve waves) and 25.8 us (six waves of two rows each, 52.7 KB of LDS:
+  // still two rings per CU). Over 512 threads with the twiddles read from the
+  // global table (52.3 KB of LDS, three rings per CU, the whole T511 launch
+  // resident) it takes 19.4 us against 21.0 us over 1024 threads with an LDS
+  // table (64.5 KB, two rings per CU).
+  if (mode == SYNTH_NONLINEAR && g.M == 1536) {
+    const size_t lds = sizeof(double2) * (size_t)(2 * padded_len(1536));
+    hipLaunchKernelGGL((k_ring<1536, 512, 1536, true>), grid, dim3(512), lds, s, g, plan, mode,
+                       grid_out);
+    return hipGetLastError();
+  }
   if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
     const size_t lds = ring_nl_lds_bytes(g.M);
     if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384>), grid, dim3(384), lds, s, g);
