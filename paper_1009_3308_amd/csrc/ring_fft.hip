@@ -22,10 +22,12 @@
 //
 // The FFT is a mixed-radix (8, 4, 2, 5, 3) Stockham transform done in place in
 // LDS: each stage reads R values at stride M/R into registers, applies
-// twiddles from a half table exp(-2 pi i e / M), e < M/2, kept in LDS, performs
-// a radix-R butterfly and writes back in autosort order after a barrier. The
-// two inverse transforms run in the same stages. With the odd radices last,
-// the stage strides are powers of two and the index arithmetic is shifts.
+// twiddles from a half table exp(-2 pi i e / M), e < M/2 (an LDS copy, or the
+// global table through L1 where the LDS is better spent on more rings per CU),
+// performs a radix-R butterfly and writes back in autosort order after a
+// barrier. The two inverse transforms run in the same stages. With the odd
+// radices last, the stage strides are powers of two and the index arithmetic
+// is shifts.
 #include <type_traits>
 
 #include "nse_internal.h"
@@ -553,26 +555,20 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
   extern __shared__ double2 lds[];
-  double2* tw = lds + 6 * PS;
+  const double2* tw = g.tw;  // twiddle half table, read through L1
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t fstride = (int64_t)(N + 1) * nlat;
   const double2* F0 = g.F + (int64_t)b * 4 * fstride + lat;
 
   // loads: every spectrum value once (thread t: order m = t mod (N+1) of pair
-  // a = t / (N+1), both fields of the pair) and the twiddle half table, all
-  // requested before the first LDS write; X_a[m] = G^f_m + i G^f'_m goes to row
+  // a = t / (N+1), both fields of the pair), all requested before the first LDS
+  // write; X_a[m] = G^f_m + i G^f'_m goes to row
   // 3a + m mod 3 at m / 3 and X_a[M - m] = conj(G^f_m) + i conj(G^f'_m) to row
   // 3a + (M - m) mod 3 at (M - m) / 3
-  constexpr int KT = (M / 2 + NT - 1) / NT;
   constexpr int KI = (2 * (S + 1) + NT - 1) / NT;  // N + 1 <= M / 3 + 1 = S + 1
   const int n1 = N + 1;
-  double2 tv[KT], ga[KI], gb[KI];
-#pragma unroll
-  for (int i = 0; i < KT; ++i) {
-    const int j = threadIdx.x + i * NT;
-    if (j < M / 2) tv[i] = g.tw[j];
-  }
+  double2 ga[KI], gb[KI];
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
     const int idx = threadIdx.x + i * NT;
@@ -589,11 +585,6 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
   // own mirror and is folded twice by the analysis
   const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
-#pragma unroll
-  for (int i = 0; i < KT; ++i) {
-    const int j = threadIdx.x + i * NT;
-    if (j < M / 2) tw[j] = tv[i];
-  }
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
     const int idx = threadIdx.x + i * NT;
@@ -668,24 +659,18 @@ __global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;
   extern __shared__ double2 lds[];
-  double2* tw = lds + 9 * PS;
+  const double2* tw = g.tw;  // twiddle half table, read through L1
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t fstride = (int64_t)(N + 1) * nlat;
   const double2* F5 = g.Fa + (int64_t)b * 5 * fstride + lat;
 
   // loads: thread t takes order m = t mod (N+1) of array a = t / (N+1) (both
-  // fields of a forward pair, or the fifth field for a = 2) and the twiddle
-  // half table, all requested before the first LDS write
-  constexpr int KT = (M / 2 + NT - 1) / NT;
+  // fields of a forward pair, or the fifth field for a = 2), all requested
+  // before the first LDS write
   constexpr int KI = (3 * (S + 1) + NT - 1) / NT;  // N + 1 <= S + 1
   const int n1 = N + 1;
-  double2 tv[KT], ga[KI], gb[KI];
-#pragma unroll
-  for (int i = 0; i < KT; ++i) {
-    const int j = threadIdx.x + i * NT;
-    if (j < M / 2) tv[i] = g.tw[j];
-  }
+  double2 ga[KI], gb[KI];
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
     const int idx = threadIdx.x + i * NT;
@@ -700,11 +685,6 @@ __global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
   const double x = g.mu[p];
   const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
   const double clat = (6.283185307179586477 / M) * g.w[p];
-#pragma unroll
-  for (int i = 0; i < KT; ++i) {
-    const int j = threadIdx.x + i * NT;
-    if (j < M / 2) tw[j] = tv[i];
-  }
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
     const int idx = threadIdx.x + i * NT;
@@ -1051,8 +1031,9 @@ hipError_t ring_dispatch(int M, F&& launch) {
   return launch(integral_constant<int, kMaxM>{}, integral_constant<int, 512>{}, integral_constant<int, 0>{});
 }
 
-// the split adjoint ring: nine rows of S + S/16 + 1 points and the twiddle half table
-size_t ring_adj_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(9 * wave_row(M / 3) + M / 2); }
+// the split adjoint ring: nine rows of S + S/16 + 1 points (the twiddles are
+// read from the global table; an LDS copy took the T255 ring from 8.2 to 8.8 us)
+size_t ring_adj_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(9 * wave_row(M / 3)); }
 
 hipError_t launch_ring_adjoint(const GroupView& g, const FftPlan& plan, hipStream_t s) {
   dim3 grid(xcd_grid(g.nlat, 8), g.nb);
@@ -1081,7 +1062,7 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
   });
 }
 
-size_t ring_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(6 * wave_row(M / 3) + M / 2); }
+size_t ring_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(6 * wave_row(M / 3)); }
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s) {
