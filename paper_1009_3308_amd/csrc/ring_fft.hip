@@ -212,6 +212,11 @@ template <> struct CtPlan<192> { static constexpr int n = 3; static constexpr in
 template <> struct CtPlan<384> { static constexpr int n = 4; static constexpr int r[4] = {8, 4, 4, 3}; };
 template <> struct CtPlan<768> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 4, 3}; };
 template <> struct CtPlan<1536> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 8, 3}; };
+// M = 320 (N = 100 on 160 x 320, the grid of the paper's Example 2): radix 5
+// last, so the product and the forward store run as separate passes
+template <> struct CtPlan<320> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 5}; };
+// plans whose last stage is radix 3 at stride M/3 (fused product and store)
+template <int M> constexpr bool ct_fused() { return CtPlan<M>::n > 0 && CtPlan<M>::r[CtPlan<M>::n - 1] == 3; }
 
 constexpr int ct_log2(int x) { return x <= 1 ? 0 : 1 + ct_log2(x / 2); }
 
@@ -828,7 +833,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   if (gate_closed(g)) return;
   __syncthreads();
   const double inv_sin2 = 1.0 / sin2;
-  if constexpr (CM > 0) {
+  if constexpr (CM > 0 && ct_fused<CM>()) {
     fft_ct_inverse_product<CM, 0, 1, NT>(A0, tw, inv_sin2);
   } else {
     fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, 1.0);
@@ -849,7 +854,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
   // W[b][m][lat]: stride nlat between orders (the eight rings of an XCD chunk
   // fill whole cache lines of one order)
   double2* Wl = g.W + (int64_t)b * (N + 1) * nlat + lat;
-  if constexpr (CM > 0) {
+  if constexpr (CM > 0 && ct_fused<CM>()) {
     fft_ct_forward_store<CM, 0, 1, NT>(A0, tw, c, Wl, nlat, N);
   } else {
     fft_any<1, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
@@ -1019,6 +1024,7 @@ hipError_t ring_dispatch(int M, F&& launch) {
     case 48: return launch(integral_constant<int, 48>{}, integral_constant<int, 64>{}, integral_constant<int, 48>{});
     case 96: return launch(integral_constant<int, 96>{}, integral_constant<int, 64>{}, integral_constant<int, 96>{});
     case 192: return launch(integral_constant<int, 192>{}, integral_constant<int, 128>{}, integral_constant<int, 192>{});
+    case 320: return launch(integral_constant<int, 320>{}, integral_constant<int, 256>{}, integral_constant<int, 320>{});
     case 384: return launch(integral_constant<int, 384>{}, integral_constant<int, 256>{}, integral_constant<int, 384>{});
     case 768: return launch(integral_constant<int, 768>{}, integral_constant<int, 512>{}, integral_constant<int, 768>{});
     case 1536: return launch(integral_constant<int, 1536>{}, integral_constant<int, 1024>{}, integral_constant<int, 1536>{});
