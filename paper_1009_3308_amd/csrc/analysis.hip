@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64 * anal_waves(R)) void k_analysis_otf(GroupView g
   // the step update's inputs of degree kt + t (t < kAnalTile), kept until the epilogue
   double2 din[kDegreeInputs];
   const bool dthread = (int)threadIdx.x < kAnalTile && kt + (int)threadIdx.x <= N - m;
-  if (dthread) load_degree_inputs(g, out, b, m, kt + threadIdx.x, din);
+  if (dthread) load_degree_inputs<NDF>(g, out, b, m, kt + threadIdx.x, din);
   // recurrence pairs of the tile's degrees (k >= 2 of the order, from the
   // group's coefficient table; zero past degree N+1, whose values are not used)
   if ((int)threadIdx.x < kAnalTile) {

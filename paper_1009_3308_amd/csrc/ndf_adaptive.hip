@@ -6,7 +6,7 @@
 // ndf_control.h on the previous sweep's norms and, when an attempt has just
 // been opened, its prepare.
 #include "lane_ops.h"
-#include "ndf_control.h"
+#include "ndf_device.h"
 
 namespace nse {
 
@@ -14,76 +14,6 @@ namespace {
 
 __device__ inline double2 zero2() { return make_double2(0.0, 0.0); }
 __device__ inline double abs2(double2 z) { return z.x * z.x + z.y * z.y; }
-
-// The control block, copied through LDS in 8-byte words.
-constexpr int kCtlWords = sizeof(NdfCtl) / sizeof(unsigned long long);
-static_assert(sizeof(NdfCtl) % sizeof(unsigned long long) == 0, "8-byte words");
-
-// Accepted-step update of the differences, rescaling to a new step and the
-// predictor of the next attempt for state slot s (ycopy, if given, also
-// receives the predictor: the first iterate of a device-controlled attempt).
-struct PrepareParams {
-  int accept, k_acc, transform, k, predict;
-  const double2* dacc;
-  const double (*R)[kNdfMaxOrder + 1];
-};
-
-__device__ inline void prepare_element(const NdfArgs& a, const PrepareParams& pp, int64_t s,
-                                       double2* ycopy) {
-  const int k = pp.k;
-  double2 D[kNdfDepth];
-#pragma unroll
-  for (int j = 0; j < kNdfDepth; ++j) D[j] = (j < a.depth) ? a.D[(int64_t)j * a.S + s] : zero2();
-  if (pp.accept) {
-    // nabla^{k+1} y_{n+1} = d, nabla^{k+2} y_{n+1} = d - nabla^{k+1} y_n,
-    // nabla^j y_{n+1} = nabla^j y_n + nabla^{j+1} y_{n+1}
-    const int ka = pp.k_acc;
-    const double2 d = pp.dacc[s];
-#pragma unroll
-    for (int j = 0; j < kNdfDepth; ++j)
-      if (j == ka + 2) D[j] = make_double2(d.x - D[j - 1].x, d.y - D[j - 1].y);
-#pragma unroll
-    for (int j = 0; j < kNdfDepth; ++j)
-      if (j == ka + 1) D[j] = d;
-#pragma unroll
-    for (int j = kNdfDepth - 2; j >= 0; --j)
-      if (j <= ka) D[j] = make_double2(D[j].x + D[j + 1].x, D[j].y + D[j + 1].y);
-  }
-  if (pp.transform) {
-#pragma unroll
-    for (int j = 0; j < kNdfDepth; ++j) {
-      double2 v = zero2();
-      if (j <= k) {
-#pragma unroll
-        for (int i = 0; i <= kNdfMaxOrder; ++i)
-          if (i >= j && i <= k) {
-            v.x += pp.R[j][i] * D[i].x;
-            v.y += pp.R[j][i] * D[i].y;
-          }
-      }
-      D[j] = v;  // rows are computed from D[i >= j] before D[j] is replaced
-    }
-  }
-  if (pp.accept || pp.transform) {
-#pragma unroll
-    for (int j = 0; j < kNdfDepth; ++j)
-      if (j < a.depth) a.D[(int64_t)j * a.S + s] = D[j];
-  }
-  if (pp.predict) {
-    double2 y = D[0], p = zero2();
-#pragma unroll
-    for (int j = 1; j <= kNdfMaxOrder; ++j)
-      if (j <= k) {
-        y.x += D[j].x;
-        y.y += D[j].y;
-        p.x += a.gam[j] * D[j].x;
-        p.y += a.gam[j] * D[j].y;
-      }
-    a.y0[s] = y;
-    a.psi[s] = p;
-    if (ycopy) ycopy[s] = y;
-  }
-}
 
 // Host-controlled prepare (its parameters in the arguments); clears the sweep norms.
 __global__ __launch_bounds__(256) void k_ndf_prepare(NdfArgs a) {
@@ -128,29 +58,15 @@ __global__ __launch_bounds__(256) void k_ndf_step(NdfArgs a, NdfStepArgs st) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int p = 0;
-    if (sc.fresh) {
-      sc.fresh = 0;
-      p = sc.running;
-    } else if (sc.running) {
-      double row[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) row[q] = sqrt(norm[q]);
-      const int r = ndf_decide(sc, row, st.sched, 1 - st.sel);
-      if (r == NDF_ENDED) {
-        if (blockIdx.x == 0) st.log[(sc.nlog - 1) % kNdfLogCap] = sc.rec;
-        p = sc.running;
-      }
-    }
-    prep = p;
+    prep = ndf_slot_decide(sc, norm, st, blockIdx.x == 0);
+    sc.prep_in_analysis = 0;  // this kernel applies the whole prepare
   }
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t w2 = s0; w2 < a.spread_words; w2 += stride) st.spread_clear[w2] = 0ull;
   if (prep) {
-    PrepareParams pp{sc.prep_accept, sc.prep_k_acc,   sc.prep_transform, sc.prep_k,
-                     sc.prep_predict, a.dsel[sc.prep_dsel], sc.prepR};
+    const PrepareParams pp = prepare_params(sc, a.dsel);
     for (int64_t s = s0; s < a.S; s += stride) prepare_element(a, pp, s, a.yout);
   }
   if (blockIdx.x == 0) {

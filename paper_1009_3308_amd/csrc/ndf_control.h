@@ -111,6 +111,9 @@ struct NdfCtl {
   int done;    // t reached t_end
   int status;  // NDF_OK or the NDF_FAIL_* that stopped the run
   int prep_accept, prep_k_acc, prep_dsel, prep_transform, prep_k, prep_predict;
+  // 1: this slot's prepare left the update of the differences to the analysis
+  // epilogue (the synthesis did the step kernel's work), 0: already applied
+  int prep_in_analysis, pad0;
   double prepR[kNdfMaxOrder + 1][kNdfMaxOrder + 1];
   // counters
   long long accepted, error_failures, newton_failures, evaluations, nlog;
@@ -368,5 +371,16 @@ struct NdfStepArgs {
   nse_forcing_schedule sched;
 };
 hipError_t launch_ndf_step(const NdfArgs& a, const NdfStepArgs& st, hipStream_t s);
+// The synthesis of sweep slot st.sel with the step kernel's work in its
+// prologue, for one group whose nonlinear synthesis is the FP64 kernel with one
+// latitude per lane and whose launch is resident at once (synthesis_takes_step):
+// every workgroup runs the controller step; the workgroup of order 0, tile 0,
+// member 0 writes the control block, the log and the cleared norm row; when an
+// attempt opens every workgroup forms its order's predictor from the updated
+// differences without storing them (the first latitude tile stores y0, psi and
+// the iterate) and the analysis epilogue stores the differences. Not gated.
+bool synthesis_takes_step(const GroupView& g);
+hipError_t launch_synthesis_step(const GroupView& g, const SynthInput& in, const NdfArgs& a,
+                                 const NdfStepArgs& st, hipStream_t s);
 
 }  // namespace nse

@@ -532,7 +532,8 @@ nse_status ensure_aux_streams(nse_ctx* c) {
 // from it and joined back, so that the chains of different truncations overlap
 // on the GPU (inside a captured graph the fork and the join become edges).
 nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out,
-                         const int* gate = nullptr) {
+                         const int* gate = nullptr, const NdfArgs* step_a = nullptr,
+                         const NdfStepArgs* step = nullptr) {
   const bool fork = !c->profiling && c->groups.size() > 1;
   if (fork) {
     nse_status s = ensure_aux_streams(c);
@@ -553,8 +554,14 @@ nse_status enqueue_chain(nse_ctx* c, const SynthInput& in, const AnalOutput& out
       continue;
     }
     nse_status s;
-    s = timed_launch(c, NSE_KERNEL_SYNTHESIS,
-                     [&] { return launch_synth_any(v, in, SYNTH_NONLINEAR, c->stream); });
+    // with `step` the synthesis also runs the sweep slot's controller step and
+    // decides for itself whether the slot runs (it writes the gate flag)
+    GroupView vs = v;
+    if (step) vs.gate = nullptr;
+    s = timed_launch(c, NSE_KERNEL_SYNTHESIS, [&] {
+      return step ? launch_synthesis_step(vs, in, *step_a, *step, c->stream)
+                  : launch_synth_any(v, in, SYNTH_NONLINEAR, c->stream);
+    });
     if (s != NSE_OK) return s;
     s = timed_launch(c, NSE_KERNEL_RING,
                      [&] { return launch_ring(v, g.plan, SYNTH_NONLINEAR, nullptr, c->stream); });
@@ -842,7 +849,8 @@ bool ndf_fusable(const nse_ctx* c) {
 // the analysis epilogue: the iterate y in, the correction to buffer sel (the
 // previous one in 1 - sel), the norms to spread row sel, the control block
 // written by the slot's k_ndf_step.
-nse_status ndf_sweep_fused(nse_ctx* c, int sel) {
+nse_status ndf_sweep_fused(nse_ctx* c, int sel, const NdfArgs* step_a = nullptr,
+                           const NdfStepArgs* step = nullptr) {
   const NdfCtl* ctl = c->d_ctl + (1 - sel);
   SynthInput in{};
   in.nsrc = 1;
@@ -864,7 +872,11 @@ nse_status ndf_sweep_fused(nse_ctx* c, int sel) {
   out.kmax = c->ad.p.max_order;
   const double r = c->ad.p.atol / c->ad.p.rtol;
   out.thr2 = r * r;
-  return enqueue_chain(c, in, out, &ctl->running);
+  out.Dw = c->d_ndf;
+  out.dacc[0] = ndf_buf(c, 3);
+  out.dacc[1] = ndf_buf(c, 4);
+  out.ddepth = c->ndf_depth;
+  return enqueue_chain(c, in, out, &ctl->running, step_a, step);
 }
 
 nse_status ndf_failure(nse_ctx* c, int code) {
@@ -927,6 +939,9 @@ nse_status capture_attempt_graph(nse_ctx* c) {
   NSE_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   nse_status s = NSE_OK;
   const bool fused = ndf_fusable(c);
+  // the synthesis takes over the step kernel (one launch fewer per sweep) when
+  // it is the single-latitude FP64 kernel and its launch is resident at once
+  const bool in_synth = fused && synthesis_takes_step(c->groups[0].view());
   for (int j = 0; j < kSlotsPerGraph && s == NSE_OK; ++j) {
     const int sel = j & 1;
     NdfArgs a = ndf_args(c);
@@ -942,6 +957,10 @@ nse_status capture_attempt_graph(nse_ctx* c) {
     st.sel = sel;
     st.log = c->d_log;
     st.sched = c->ad.sched;
+    if (in_synth) {
+      s = ndf_sweep_fused(c, sel, &a, &st);
+      continue;
+    }
     const hipError_t e = launch_ndf_step(a, st, c->stream);
     if (e != hipSuccess) {
       s = hip_fail(c, e, "launch_ndf_step");

@@ -151,6 +151,11 @@ struct AnalOutput {
   unsigned long long* nrow;  // the sweep's spread norm row (squares, IEEE bits, atomic max)
   int kmax;
   double thr2;               // (atol / rtol)^2
+  // when ctl->prep_in_analysis: the epilogue applies the slot's update of the
+  // differences D[0..ddepth) (accepted correction from dacc[ctl->prep_dsel])
+  double2* Dw;
+  const double2* dacc[2];
+  int ddepth;
 };
 
 // Adaptive NDF integrator (Section 4.2, eq. (ode_disc) in backward differences

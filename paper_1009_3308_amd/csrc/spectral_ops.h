@@ -3,7 +3,7 @@
 // the per-degree epilogue of the analysis (post-scaling and time step).
 #pragma once
 
-#include "ndf_control.h"
+#include "ndf_device.h"
 #include "nse_internal.h"
 
 namespace nse {
@@ -121,19 +121,39 @@ __device__ inline void build_panel(double2* pan, const double2* a, int N, int m,
 constexpr int kDegreeInputs = kMaxStepCoef;  // forcing + up to kMaxStepCoef - 1 history slots
 // ANAL_NDF: in[0] = f, in[1] = D[0], in[2] = y0, in[3] = psi, in[4] = dprev,
 // in[5] = D[order] (order > 1), in[6] = D[order + 1] (order < kmax).
+// NDF: the kernel instance serves ANAL_NDF (the mode's inputs are compiled
+// into that instance only).
+template <bool NDF = false>
 __device__ inline void load_degree_inputs(const GroupView& g, const AnalOutput& out, int b, int m,
                                           int k, double2* in) {
   if (out.mode == ANAL_NONLINEAR) return;
   const int64_t slot = g.off[b] + coeff_offset(g.N, m) + k;
-  if (out.mode == ANAL_NDF) {
+  if (NDF && out.mode == ANAL_NDF) {
     const double2 z = make_double2(0.0, 0.0);
     const int64_t S = out.state_count;
-    const int q = out.ctl->k;
+    const NdfCtl& c = *out.ctl;
+    const int q = c.k;
     in[0] = out.forcing ? out.forcing[slot] : z;
-    in[1] = out.D[slot];
     in[2] = out.y0[slot];
     in[3] = out.psi[slot];
-    in[4] = (out.dprev && out.ctl->sweep != 0) ? out.dprev[slot] : z;  // none on a first sweep
+    in[4] = (out.dprev && c.sweep != 0) ? out.dprev[slot] : z;  // none on a first sweep
+    if (c.prep_in_analysis && (c.prep_accept || c.prep_transform)) {
+      // the attempt opened in this slot: its update of the differences, which
+      // the synthesis only used for the predictor, is applied here (each
+      // element by one thread)
+      double2 D[kNdfDepth];
+      prepared_differences(out.D, S, out.ddepth, prepare_params(c, out.dacc), slot, D);
+      in[1] = D[0];
+      in[5] = in[6] = z;
+#pragma unroll
+      for (int j = 0; j < kNdfDepth; ++j) {
+        if (j < out.ddepth) out.Dw[(int64_t)j * S + slot] = D[j];
+        if (j == q && q > 1) in[5] = D[j];
+        if (j == q + 1 && q < out.kmax) in[6] = D[j];
+      }
+      return;
+    }
+    in[1] = out.D[slot];
     in[5] = q > 1 ? out.D[(int64_t)q * S + slot] : z;
     in[6] = q < out.kmax ? out.D[(int64_t)(q + 1) * S + slot] : z;
     return;

@@ -18,6 +18,7 @@
 // latitudes each.
 #include <type_traits>
 
+#include "lane_ops.h"
 #include "spectral_ops.h"
 
 namespace nse {
@@ -261,8 +262,17 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 // where the panel form needs five, and D[l] has the parity opposite to Pbar[l,m] under
 // mu -> -mu, so its terms go to the other half of the even/odd split. Tiles,
 // latitudes per lane (R) and the cross-wave sums are those of k_synthesis.
-template <int R>
-__global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
+// STEP: the synthesis of a device-controlled sweep slot that also does the
+// slot's controller step (as k_ndf_step): the control block and the previous
+// sweep's norms are read first and thread 0 of every workgroup runs the
+// controller (the same inputs give every workgroup the same result); when an
+// attempt opens, each workgroup forms its order's predictor from the updated
+// differences as its input, the first latitude tile stores y0, psi and the
+// iterate, and the analysis epilogue of the slot stores the differences (the
+// tiles of an order all read the old ones here).
+template <int R, bool STEP>
+__device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const SynthInput& in,
+                                                   const NdfArgs* na, const NdfStepArgs* ns) {
   constexpr int kRed = 16;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
@@ -321,19 +331,83 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   }
   const int64_t base = g.off[b] + coeff_offset(N, m);
   const int64_t rbase = rec_slot(N, m, m);
+  // STEP: one degree per thread (N + 1 + kOtfBatch <= kSynthThreads), its
+  // iterate and coefficients requested before the controller step
+  double2 y1 = make_double2(0.0, 0.0), c1 = y1, e1 = y1;
+  if constexpr (STEP) {
+    const int k = threadIdx.x, l = m + k;
+    if (k < K && l >= 1) y1 = in.src[0][base + k];
+    if (k < K) {
+      c1 = g.rec_a[rbase + k];
+      e1 = g.rec_g[rbase + k];
+    }
+  }
+  int prep = 0;
+  NdfCtl* sc = nullptr;
+  if constexpr (STEP) {
+    // the control block after the coefficient arrays and the cross-wave buffer
+    const int arrays = 4 * (N + 1 + kOtfBatch), red = kSynthWaves * kRed * 64 / 2;
+    sc = reinterpret_cast<NdfCtl*>(sh + (arrays > red ? arrays : red));
+    double* norm = reinterpret_cast<double*>(sc + 1);
+    int* prepf = reinterpret_cast<int*>(norm + 4);
+    const unsigned long long* cw = reinterpret_cast<const unsigned long long*>(ns->ctl_in);
+    constexpr int KW = (kCtlWords + kSynthThreads - 1) / kSynthThreads;
+    unsigned long long w[KW];
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      const int j = threadIdx.x + kSynthThreads * i;
+      if (j < kCtlWords) w[i] = cw[j];
+    }
+    if (threadIdx.x < kNdfSpread) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[q] = __longlong_as_double((long long)ns->spread_in[threadIdx.x * kNdfSpreadStride + q]);
+      const double mx = lane_max4(v);  // lane 16 q: the maximum of v[q]
+      if ((threadIdx.x & 15) == 0) norm[threadIdx.x >> 4] = mx;
+    }
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(sc);
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      const int j = threadIdx.x + kSynthThreads * i;
+      if (j < kCtlWords) dst[j] = w[i];
+    }
+    __syncthreads();
+    const bool first = blockIdx.x == 0 && blockIdx.y == 0;  // order 0, tile 0, member 0
+    if (threadIdx.x == 0) {
+      *prepf = ndf_slot_decide(*sc, norm, *ns, first);
+      sc->prep_in_analysis = *prepf;
+    }
+    __syncthreads();
+    if (first) {
+      const unsigned long long* from = reinterpret_cast<const unsigned long long*>(sc);
+      unsigned long long* to = reinterpret_cast<unsigned long long*>(ns->ctl_out);
+      for (int j = threadIdx.x; j < kCtlWords; j += blockDim.x) to[j] = from[j];
+      for (int64_t j = threadIdx.x; j < na->spread_words; j += blockDim.x) ns->spread_clear[j] = 0ull;
+    }
+    if (!sc->running) return;  // no attempt open: the slot does nothing (uniform)
+    prep = *prepf;
+  }
   for (int k = threadIdx.x; k < K + kOtfBatch; k += blockDim.x) {
     const int l = m + k;
     // input state alpha[l] = sum_i coef_i src_i[l] (l = 1..N; real at m = 0)
     double2 src[kMaxSources];
-#pragma unroll
-    for (int i = 0; i < kMaxSources; ++i) {
-      src[i] = make_double2(0.0, 0.0);
-      if (i < in.nsrc && k < K && l >= 1) src[i] = in.src[i][base + k];
-    }
     double2 c = make_double2(0.0, 0.0), e = c;
-    if (k < K) {
-      c = g.rec_a[rbase + k];
-      e = g.rec_g[rbase + k];
+    if constexpr (STEP) {
+#pragma unroll
+      for (int i = 0; i < kMaxSources; ++i) src[i] = i == 0 ? y1 : make_double2(0.0, 0.0);
+      c = c1;
+      e = e1;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kMaxSources; ++i) {
+        src[i] = make_double2(0.0, 0.0);
+        if (i < in.nsrc && k < K && l >= 1) src[i] = in.src[i][base + k];
+      }
+      if (k < K) {
+        c = g.rec_a[rbase + k];
+        e = g.rec_g[rbase + k];
+      }
     }
     double2 v = make_double2(0.0, 0.0);
 #pragma unroll
@@ -341,6 +415,23 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
       if (i < in.nsrc) {
         v.x += in.coef[i] * src[i].x;
         v.y += in.coef[i] * src[i].y;
+      }
+    }
+    if constexpr (STEP) {
+      if (prep && k < K) {
+        const PrepareParams pp = prepare_params(*sc, na->dsel);
+        if (pp.predict) {
+          const int64_t s = base + k;
+          double2 D[kNdfDepth], y, p;
+          prepared_differences(na->D, na->S, na->depth, pp, s, D);
+          ndf_predictor(D, pp.k, na->gam, y, p);
+          if (tile == 0) {
+            na->y0[s] = y;
+            na->psi[s] = p;
+            na->yout[s] = y;
+          }
+          if (l >= 1) v = y;
+        }
       }
     }
     if (m == 0) v.y = 0.0;
@@ -354,7 +445,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   }
   // an ended attempt of a device-controlled run: checked once the loads are in
   // flight (nothing is stored before this barrier), so the flag costs no wait
-  if (gate_closed(g)) return;
+  if (!STEP && gate_closed(g)) return;
   __syncthreads();
 
   // acc[r][4 f + 2 q + c]: field f, q = 0 even / 1 odd part, c = 0 re / 1 im
@@ -464,6 +555,16 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, Sy
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
+  synthesis_adv_body<R, false>(g, in, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv_step(GroupView g, SynthInput in,
+                                                                      NdfArgs a, NdfStepArgs st) {
+  synthesis_adv_body<1, true>(g, in, &a, &st);
+}
+
 size_t synthesis_adv_lds_bytes(int N) {
   const int arrays = 4 * (N + 1 + kOtfBatch);
   const int red = kSynthWaves * 16 * 64 / 2;
@@ -513,6 +614,25 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
   } else {
     return launch_synthesis_otf4<double>(g, in, mode, s);
   }
+  return hipGetLastError();
+}
+
+// The controller step needs about 240 VGPRs (two waves per SIMD): taken into
+// the synthesis only while the launch stays resident at once (two four-wave
+// workgroups per CU).
+bool synthesis_takes_step(const GroupView& g) {
+  const int ntile = (g.nh + 63) / 64;
+  return g.precision == NSE_PREC_FP64 && g.mb_synth < 2 && g.nh < 256 &&
+         g.N + 1 + kOtfBatch <= kSynthThreads && (int64_t)(g.N + 1) * ntile * g.nb <= 512;
+}
+
+hipError_t launch_synthesis_step(const GroupView& g, const SynthInput& in, const NdfArgs& a,
+                                 const NdfStepArgs& st, hipStream_t s) {
+  if (!synthesis_takes_step(g)) return hipErrorInvalidValue;
+  const int ntile = (g.nh + 63) / 64;
+  dim3 grid(xcd_grid((g.N + 1) * ntile, ntile), g.nb);
+  const size_t lds = synthesis_adv_lds_bytes(g.N) + sizeof(NdfCtl) + 6 * sizeof(double);
+  hipLaunchKernelGGL(k_synthesis_adv_step, grid, dim3(kSynthThreads), lds, s, g, in, a, st);
   return hipGetLastError();
 }
 

@@ -107,11 +107,15 @@ def test_adaptive_matches_oracle(N, nu, T, rtol, max_newton):
     assert stats["waits"] <= 2 + len(glog) // 4, stats
 
 
-def test_adaptive_wide_grid_matches_oracle():
-    """The device-controlled sweeps on a grid of more than 192 northern
-    latitudes, where each analysis wave takes two blocks of 16 degrees (one
-    recurrence, two lane reductions, the corrector and the norm maxima of both)."""
-    N, nlat, nu, T = 140, 400, 1e-3, 0.3
+@pytest.mark.parametrize("N", [140, 60])
+def test_adaptive_wide_grid_matches_oracle(N):
+    """The device-controlled sweeps on a grid of 200 northern latitudes (four
+    latitudes per analysis lane, four latitude tiles per synthesis order): at
+    N = 60 the synthesis also runs the slot's controller step (every tile
+    forming its order's predictor from the old differences, the analysis
+    epilogue storing the new ones), at N = 140 (a launch too large to stay
+    resident with the controller's registers) the step kernel does."""
+    nlat, nu, T = 400, 1e-3, 0.3
     _say(f"case adaptive N={N} nlat={nlat} T={T}")
     a0 = I.initial_state(N)
     f = I.forcing(N)
