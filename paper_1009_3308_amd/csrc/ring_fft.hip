@@ -551,7 +551,11 @@ __device__ __forceinline__ void wave_fft(double2* x, const double2* tw, int lane
 // Workgroup of NT >= max(S, 384) threads per ring: waves 0..5 hold the inverse
 // transforms Y_{a,k1} (a = 0: f0 + i f1, a = 1: f2 + i f3), threads n2 < S the
 // fused pass, waves 0..2 the forward transforms.
-template <int S, int NT>
+// TWL: the twiddle half table copied to LDS (after the six rows) instead of
+// read from the global table through L1: the better choice when many members'
+// rings share the CUs (throughput), the global table when one member's rings
+// are latency-bound.
+template <int S, int NT, bool TWL>
 __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   constexpr int M = 3 * S, PS = wave_row(S);
   const int N = g.N, nlat = g.nlat;
@@ -560,7 +564,11 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   const int b = blockIdx.y;
   const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
   extern __shared__ double2 lds[];
-  const double2* tw = g.tw;  // twiddle half table, read through L1
+  double2* twl = lds + 6 * PS;
+  const double2* tw = TWL ? twl : g.tw;
+  if constexpr (TWL) {
+    for (int j = threadIdx.x; j < M / 2; j += NT) twl[j] = g.tw[j];  // ordered by the first barrier
+  }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t fstride = (int64_t)(N + 1) * nlat;
@@ -1068,7 +1076,11 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
   });
 }
 
-size_t ring_nl_lds_bytes(int M) { return sizeof(double2) * (size_t)(6 * wave_row(M / 3)); }
+// the split ring: six rows of S + S/16 + 1 points, and the twiddle half table
+// with an LDS copy
+size_t ring_nl_lds_bytes(int M, bool twl) {
+  return sizeof(double2) * (size_t)(6 * wave_row(M / 3) + (twl ? M / 2 : 0));
+}
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
                        hipStream_t s) {
@@ -1088,9 +1100,18 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
     return hipGetLastError();
   }
   if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
-    const size_t lds = ring_nl_lds_bytes(g.M);
-    if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384>), grid, dim3(384), lds, s, g);
-    else hipLaunchKernelGGL((k_ring_nl<256, 384>), grid, dim3(384), lds, s, g);
+    // many members: LDS twiddles (the ensemble's 16 x N = 255 rings: 66 us
+    // against 76 us with the global table, its 24 x N = 127 rings 58 against
+    // 75 us; one member at T255: 8.8 against 8.2 us)
+    const bool twl = g.nb >= 4;
+    const size_t lds = ring_nl_lds_bytes(g.M, twl);
+    if (g.M == 384) {
+      if (twl) hipLaunchKernelGGL((k_ring_nl<128, 384, true>), grid, dim3(384), lds, s, g);
+      else hipLaunchKernelGGL((k_ring_nl<128, 384, false>), grid, dim3(384), lds, s, g);
+    } else {
+      if (twl) hipLaunchKernelGGL((k_ring_nl<256, 384, true>), grid, dim3(384), lds, s, g);
+      else hipLaunchKernelGGL((k_ring_nl<256, 384, false>), grid, dim3(384), lds, s, g);
+    }
     return hipGetLastError();
   }
   const size_t lds = ring_lds_bytes(g.M);
