@@ -548,23 +548,28 @@ __device__ __forceinline__ void wave_fft(double2* x, const double2* tw, int lane
   }
 }
 
-// Workgroup of NT >= max(S, 384) threads per ring: waves 0..5 hold the inverse
-// transforms Y_{a,k1} (a = 0: f0 + i f1, a = 1: f2 + i f3), threads n2 < S the
-// fused pass, waves 0..2 the forward transforms.
-// TWL: the twiddle half table copied to LDS (after the six rows) instead of
-// read from the global table through L1: the better choice when many members'
+// Workgroup of NR neighbouring rings, NT / NR >= max(S, 384) threads per ring:
+// waves 6 r .. 6 r + 5 hold the inverse transforms Y_{a,k1} of ring r (a = 0:
+// f0 + i f1, a = 1: f2 + i f3) on LDS rows 6 r + 3 a + k1, threads
+// r NT / NR + n2 (n2 < S) the fused pass of ring r, waves 3 r .. 3 r + 2 its
+// forward transforms. With NR = 2 the loads of the two rings' spectra pair up
+// on the same cache lines (lanes 2 j and 2 j + 1 read the two latitudes of one
+// order): T255 ring 8.2 -> 7.6 us, the launch's 192 workgroups leaving 64 CUs
+// idle while the others hold the two rings that the busiest CUs held before.
+// TWL: the twiddle half table copied to LDS (after the rows) instead of read
+// from the global table through L1: the better choice when many members'
 // rings share the CUs (throughput), the global table when one member's rings
 // are latency-bound.
-template <int S, int NT, bool TWL>
+template <int S, int NT, bool TWL, int NR>
 __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
-  constexpr int M = 3 * S, PS = wave_row(S);
+  constexpr int M = 3 * S, PS = wave_row(S), RT = NT / NR;
+  static_assert(RT >= S && RT >= 384, "threads per ring");
   const int N = g.N, nlat = g.nlat;
-  const int lat = xcd_item(blockIdx.x, 8);
-  if (lat >= nlat) return;
+  const int lat0 = NR * xcd_item(blockIdx.x, 8 / NR);  // XCD chunks of 8 latitudes
+  if (lat0 >= nlat) return;
   const int b = blockIdx.y;
-  const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
   extern __shared__ double2 lds[];
-  double2* twl = lds + 6 * PS;
+  double2* twl = lds + 6 * NR * PS;
   const double2* tw = TWL ? twl : g.tw;
   if constexpr (TWL) {
     for (int j = threadIdx.x; j < M / 2; j += NT) twl[j] = g.tw[j];  // ordered by the first barrier
@@ -572,38 +577,35 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t fstride = (int64_t)(N + 1) * nlat;
-  const double2* F0 = g.F + (int64_t)b * 4 * fstride + lat;
+  const double2* F0 = g.F + (int64_t)b * 4 * fstride + lat0;
 
-  // loads: every spectrum value once (thread t: order m = t mod (N+1) of pair
-  // a = t / (N+1), both fields of the pair), all requested before the first LDS
-  // write; X_a[m] = G^f_m + i G^f'_m goes to row
-  // 3a + m mod 3 at m / 3 and X_a[M - m] = conj(G^f_m) + i conj(G^f'_m) to row
-  // 3a + (M - m) mod 3 at (M - m) / 3
-  constexpr int KI = (2 * (S + 1) + NT - 1) / NT;  // N + 1 <= M / 3 + 1 = S + 1
+  // loads: every spectrum value once (thread t: ring rr = t mod NR, order
+  // m = t' mod (N+1) of pair a = t' / (N+1), t' = t / NR, both fields of the
+  // pair), all requested before the first LDS write; X_a[m] = G^f_m + i G^f'_m
+  // goes to row 3a + m mod 3 of its ring at m / 3 and X_a[M - m] =
+  // conj(G^f_m) + i conj(G^f'_m) to row 3a + (M - m) mod 3 at (M - m) / 3
+  constexpr int KI = (2 * (S + 1) + RT - 1) / RT;  // N + 1 <= M / 3 + 1 = S + 1
   const int n1 = N + 1;
+  const int rr = threadIdx.x % NR, tt = threadIdx.x / NR;
+  const bool rvalid = lat0 + rr < nlat;  // an odd last ring pair holds one ring
   double2 ga[KI], gb[KI];
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
-    const int idx = threadIdx.x + i * NT;
+    const int idx = tt + i * RT;
     ga[i] = gb[i] = make_double2(0.0, 0.0);
-    if (idx < 2 * n1) {
+    if (idx < 2 * n1 && rvalid) {
       const int a = idx >= n1 ? 1 : 0, m = idx - a * n1;
-      const double2* Fa = F0 + (int64_t)(2 * a) * fstride + (int64_t)m * nlat;
+      const double2* Fa = F0 + (int64_t)(2 * a) * fstride + (int64_t)m * nlat + rr;
       ga[i] = Fa[0];
       gb[i] = Fa[fstride];
     }
   }
-  const double x = g.mu[p];
-  const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
-  // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
-  // own mirror and is folded twice by the analysis
-  const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
-    const int idx = threadIdx.x + i * NT;
+    const int idx = tt + i * RT;
     if (idx < 2 * n1) {
       const int a = idx >= n1 ? 1 : 0, m = idx - a * n1;
-      double2* rows = lds + 3 * a * PS;
+      double2* rows = lds + (6 * rr + 3 * a) * PS;
       if (m == 0) {
         rows[0] = make_double2(ga[i].x, gb[i].x);
       } else {
@@ -613,45 +615,63 @@ __global__ __launch_bounds__(NT) void k_ring_nl(GroupView g) {
       }
     }
   }
-  // the zero band N < k < M - N of both arrays
-  for (int t = threadIdx.x; t < 2 * (M - 2 * N - 1); t += NT) {
-    const int a = t >= M - 2 * N - 1 ? 1 : 0;
-    const int k = N + 1 + t - a * (M - 2 * N - 1);
-    lds[(3 * a + k % 3) * PS + pad(k / 3)] = make_double2(0.0, 0.0);
+  // the zero band N < k < M - N of both arrays of every ring
+  const int zb = M - 2 * N - 1;
+  for (int t = threadIdx.x; t < NR * 2 * zb; t += NT) {
+    const int r = t / (2 * zb), u = t - r * 2 * zb;
+    const int a = u >= zb ? 1 : 0;
+    const int k = N + 1 + u - a * zb;
+    lds[(6 * r + 3 * a + k % 3) * PS + pad(k / 3)] = make_double2(0.0, 0.0);
   }
   // an ended attempt of a device-controlled run: checked once the loads are in
   // flight (nothing is stored before this barrier), so the flag costs no wait
   if (gate_closed(g)) return;
   __syncthreads();
-  if (wave < 6) wave_fft<S, 0, 1, 1, false>(lds + wave * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
+  if (wave < 6 * NR) wave_fft<S, 0, 1, 1, false>(lds + wave * PS, tw, lane, 0.0, nullptr, 0, 0, 0);
   __syncthreads();
-  // fused pass at n2 = threadIdx.x: inverse twiddles and radix 3 of both pairs,
-  // the grid product at S n1 + n2, forward radix 3 and twiddles
-  for (int n2 = threadIdx.x; n2 < S; n2 += NT) {
-    const double2 w1 = tw_full<M>(tw, n2), w2 = cmul(w1, w1);
-    double2 y[2][3];
+  // fused pass of ring r at n2: inverse twiddles and radix 3 of both pairs, the
+  // grid product at S n1 + n2, forward radix 3 and twiddles
+  {
+    const int r = threadIdx.x / RT, n2 = threadIdx.x - r * RT;
+    const int lat = lat0 + r;
+    if (n2 < S && lat < nlat) {
+      const int p = lat < g.nh ? lat : nlat - 1 - lat;  // northern node of the ring
+      const double x = g.mu[p];
+      const double inv_sin2 = 1.0 / ((1.0 - x) * (1.0 + x));
+      double2* rows = lds + 6 * r * PS;
+      const double2 w1 = tw_full<M>(tw, n2), w2 = cmul(w1, w1);
+      double2 y[2][3];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < 2; ++a) {
 #pragma unroll
-      for (int k1 = 0; k1 < 3; ++k1) y[a][k1] = lds[(3 * a + k1) * PS + pad(n2)];
-      y[a][1] = cmul(y[a][1], make_double2(w1.x, -w1.y));
-      y[a][2] = cmul(y[a][2], make_double2(w2.x, -w2.y));
-      butterfly<3>(y[a], 1.0);
+        for (int k1 = 0; k1 < 3; ++k1) y[a][k1] = rows[(3 * a + k1) * PS + pad(n2)];
+        y[a][1] = cmul(y[a][1], make_double2(w1.x, -w1.y));
+        y[a][2] = cmul(y[a][2], make_double2(w2.x, -w2.y));
+        butterfly<3>(y[a], 1.0);
+      }
+      double2 z[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        z[j] = make_double2((y[0][j].x * y[1][j].x - y[0][j].y * y[1][j].y) * inv_sin2, 0.0);
+      butterfly<3>(z, -1.0);
+      z[1] = cmul(z[1], w1);
+      z[2] = cmul(z[2], w2);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) rows[k1 * PS + pad(n2)] = z[k1];
     }
-    double2 z[3];
-#pragma unroll
-    for (int n1 = 0; n1 < 3; ++n1)
-      z[n1] = make_double2((y[0][n1].x * y[1][n1].x - y[0][n1].y * y[1][n1].y) * inv_sin2, 0.0);
-    butterfly<3>(z, -1.0);
-    z[1] = cmul(z[1], w1);
-    z[2] = cmul(z[2], w2);
-#pragma unroll
-    for (int k1 = 0; k1 < 3; ++k1) lds[k1 * PS + pad(n2)] = z[k1];
   }
   __syncthreads();
-  if (wave < 3) {
-    double2* Wl = g.W + (int64_t)b * (N + 1) * nlat + lat;  // W[b][m][lat]
-    wave_fft<S, 0, 1, -1, true>(lds + wave * PS, tw, lane, c, Wl, nlat, wave, N);
+  if (wave < 3 * NR) {
+    const int r = wave / 3, k1 = wave - 3 * r;
+    const int lat = lat0 + r;
+    if (lat < nlat) {
+      const int p = lat < g.nh ? lat : nlat - 1 - lat;
+      // quadrature factor (2 pi / M) w_p; the equator ring of an odd rule is its
+      // own mirror and is folded twice by the analysis
+      const double c = (6.283185307179586477 / M) * g.w[p] * (2 * p + 1 == nlat ? 0.5 : 1.0);
+      double2* Wl = g.W + (int64_t)b * (N + 1) * nlat + lat;  // W[b][m][lat]
+      wave_fft<S, 0, 1, -1, true>(lds + (6 * r + k1) * PS, tw, lane, c, Wl, nlat, k1, N);
+    }
   }
 }
 
@@ -1076,10 +1096,10 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
   });
 }
 
-// the split ring: six rows of S + S/16 + 1 points, and the twiddle half table
-// with an LDS copy
-size_t ring_nl_lds_bytes(int M, bool twl) {
-  return sizeof(double2) * (size_t)(6 * wave_row(M / 3) + (twl ? M / 2 : 0));
+// the split ring: six rows of S + S/16 + 1 points per ring, and the twiddle
+// half table with an LDS copy
+size_t ring_nl_lds_bytes(int M, int nr, bool twl) {
+  return sizeof(double2) * (size_t)(6 * nr * wave_row(M / 3) + (twl ? M / 2 : 0));
 }
 
 hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double* grid_out,
@@ -1100,17 +1120,20 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
     return hipGetLastError();
   }
   if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
-    // many members: LDS twiddles (the ensemble's 16 x N = 255 rings: 66 us
-    // against 76 us with the global table, its 24 x N = 127 rings 58 against
-    // 75 us; one member at T255: 8.8 against 8.2 us)
-    const bool twl = g.nb >= 4;
-    const size_t lds = ring_nl_lds_bytes(g.M, twl);
-    if (g.M == 384) {
-      if (twl) hipLaunchKernelGGL((k_ring_nl<128, 384, true>), grid, dim3(384), lds, s, g);
-      else hipLaunchKernelGGL((k_ring_nl<128, 384, false>), grid, dim3(384), lds, s, g);
+    // many members: one ring per workgroup with LDS twiddles (the ensemble's
+    // 16 x N = 255 rings: 66 us against 76 us with the global table, its
+    // 24 x N = 127 rings 58 against 75 us); few members: two rings per
+    // workgroup, global twiddles (one member at T255: 7.6 us against 8.2 us
+    // with one ring per workgroup and 8.8 us with LDS twiddles)
+    if (g.nb >= 4) {
+      const size_t lds = ring_nl_lds_bytes(g.M, 1, true);
+      if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384, true, 1>), grid, dim3(384), lds, s, g);
+      else hipLaunchKernelGGL((k_ring_nl<256, 384, true, 1>), grid, dim3(384), lds, s, g);
     } else {
-      if (twl) hipLaunchKernelGGL((k_ring_nl<256, 384, true>), grid, dim3(384), lds, s, g);
-      else hipLaunchKernelGGL((k_ring_nl<256, 384, false>), grid, dim3(384), lds, s, g);
+      dim3 grid2(xcd_grid((g.nlat + 1) / 2, 4), g.nb);
+      const size_t lds = ring_nl_lds_bytes(g.M, 2, false);
+      if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 768, false, 2>), grid2, dim3(768), lds, s, g);
+      else hipLaunchKernelGGL((k_ring_nl<256, 768, false, 2>), grid2, dim3(768), lds, s, g);
     }
     return hipGetLastError();
   }
