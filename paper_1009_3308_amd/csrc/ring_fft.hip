@@ -1122,13 +1122,19 @@ hipError_t launch_ring(const GroupView& g, const FftPlan& plan, int mode, double
   if (mode == SYNTH_NONLINEAR && (g.M == 384 || g.M == 768)) {
     // many members: one ring per workgroup with LDS twiddles (the ensemble's
     // 16 x N = 255 rings: 66 us against 76 us with the global table, its
-    // 24 x N = 127 rings 58 against 75 us); few members: two rings per
-    // workgroup, global twiddles (one member at T255: 7.6 us against 8.2 us
-    // with one ring per workgroup and 8.8 us with LDS twiddles)
+    // 24 x N = 127 rings 58 against 75 us); few members: global twiddles, and
+    // two rings per workgroup when there are more rings than CUs (one member
+    // at T255: 7.6 us against 8.2 us with one ring per workgroup and 8.8 us
+    // with LDS twiddles; at T127, 192 rings, one ring per workgroup: 5.7
+    // against 7.0 us)
     if (g.nb >= 4) {
       const size_t lds = ring_nl_lds_bytes(g.M, 1, true);
       if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384, true, 1>), grid, dim3(384), lds, s, g);
       else hipLaunchKernelGGL((k_ring_nl<256, 384, true, 1>), grid, dim3(384), lds, s, g);
+    } else if ((int64_t)g.nlat * g.nb <= 256) {
+      const size_t lds = ring_nl_lds_bytes(g.M, 1, false);
+      if (g.M == 384) hipLaunchKernelGGL((k_ring_nl<128, 384, false, 1>), grid, dim3(384), lds, s, g);
+      else hipLaunchKernelGGL((k_ring_nl<256, 384, false, 1>), grid, dim3(384), lds, s, g);
     } else {
       dim3 grid2(xcd_grid((g.nlat + 1) / 2, 4), g.nb);
       const size_t lds = ring_nl_lds_bytes(g.M, 2, false);
