@@ -270,10 +270,16 @@ __global__ __launch_bounds__(kSynthThreads) void k_synthesis(GroupView g, SynthI
 // differences as its input, the first latitude tile stores y0, psi and the
 // iterate, and the analysis epilogue of the slot stores the differences (the
 // tiles of an order all read the old ones here).
-template <int R, bool STEP>
+// NF = 5 (SYNTH_ADJ, the adjoint's synthesis): a fifth field
+// f4 = sum lambda^(-1/2) n_bar[l] Pbar (Pbar terms, zero at l = 0, real at m = 0,
+// times -h / (c_0 + h nu lambda) inside the step adjoint) written with the four
+// forward fields to Fa.
+template <int R, int NF, bool STEP>
 __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const SynthInput& in,
                                                    const NdfArgs* na, const NdfStepArgs* ns) {
-  constexpr int kRed = 16;
+  static_assert(NF == 4 || NF == 5, "four fields, or five in the adjoint mode");
+  static_assert(!STEP || NF == 4, "the controller step rides on the nonlinear synthesis");
+  constexpr int kRed = 4 * NF;
   constexpr int kB = (R == 1) ? kOtfBatch : 2;  // degrees per recurrence batch
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (nh + 64 * R - 1) / (64 * R);
@@ -290,6 +296,7 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
   double2* za = psi + (N + 1 + kOtfBatch);  // [K + kOtfBatch] zeta_a[l] = lambda_l psi[l]
   double2* rc = za + (N + 1 + kOtfBatch);   // [K + kOtfBatch] (a(l,m), a(l,m) / a(l-1,m))
   double2* dc = rc + (N + 1 + kOtfBatch);   // [K + kOtfBatch] ((2l+1) e(l), l)
+  double2* n5 = dc + (N + 1 + kOtfBatch);   // NF = 5: [K + kOtfBatch] lambda^(-1/2) n_bar[l]
 
   const int lane = threadIdx.x & 63;
   // the wave index is uniform across the wave, so the degree bounds are scalar
@@ -346,7 +353,7 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
   NdfCtl* sc = nullptr;
   if constexpr (STEP) {
     // the control block after the coefficient arrays and the cross-wave buffer
-    const int arrays = 4 * (N + 1 + kOtfBatch), red = kSynthWaves * kRed * 64 / 2;
+    const int arrays = NF * (N + 1 + kOtfBatch), red = kSynthWaves * kRed * 64 / 2;
     sc = reinterpret_cast<NdfCtl*>(sh + (arrays > red ? arrays : red));
     double* norm = reinterpret_cast<double*>(sc + 1);
     int* prepf = reinterpret_cast<int*>(norm + 4);
@@ -442,6 +449,17 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
     za[k] = make_double2(lam * ps.x, lam * ps.y);
     rc[k] = c;
     dc[k] = make_double2(e.x, (k < K) ? dl : 0.0);
+    if constexpr (NF == 5) {
+      // fifth field: lambda^(-1/2) n_bar, l = max(m, 1)..N, real at m = 0
+      double2 w = make_double2(0.0, 0.0);
+      if (k < K && l >= 1) {
+        const double2 nb = in.adj[base + k];
+        double r = e.y;
+        if (in.adj_step) r *= -in.adj_h / (in.adj_c0 + in.adj_h * g.nu[b] * lam);
+        w = make_double2(nb.x * r, m == 0 ? 0.0 : nb.y * r);
+      }
+      n5[k] = w;
+    }
   }
   // an ended attempt of a device-controlled run: checked once the loads are in
   // flight (nothing is stored before this barrier), so the flag costs no wait
@@ -463,6 +481,11 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
       const double2 ps = psi[0], zz = za[0], d = dc[0];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
+        if constexpr (NF == 5) {
+          const double2 w = n5[0];
+          acc[r][16] = fma(P1[r], w.x, acc[r][16]);
+          acc[r][17] = fma(P1[r], w.y, acc[r][17]);
+        }
         const double D = fma(d.y, XP1[r], -d.x * P2[r]);
         acc[r][0] = fma(P1[r], ps.x, acc[r][0]);
         acc[r][1] = fma(P1[r], ps.y, acc[r][1]);
@@ -488,13 +511,14 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
     // degrees kbs .. k1 - 1 in batches of kB (kb odd: degree kb + u is odd for
     // even u)
     for (int kb = kbs; kb < k1; kb += kB) {
-      double2 c[kB], ps[kB], zz[kB], d[kB];
+      double2 c[kB], ps[kB], zz[kB], d[kB], w5[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         c[u] = rc[kb + u];
         ps[u] = psi[kb + u];
         zz[u] = za[kb + u];
         d[u] = dc[kb + u];
+        if constexpr (NF == 5) w5[u] = n5[kb + u];
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -517,6 +541,10 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
           acc[r][9 + qd] = fma(D, zz[u].y, acc[r][9 + qd]);
           acc[r][12 + qp] = fma(v, zz[u].x, acc[r][12 + qp]);
           acc[r][13 + qp] = fma(v, zz[u].y, acc[r][13 + qp]);
+          if constexpr (NF == 5) {
+            acc[r][16 + qp] = fma(v, w5[u].x, acc[r][16 + qp]);
+            acc[r][17 + qp] = fma(v, w5[u].y, acc[r][17 + qp]);
+          }
         }
       }
     }
@@ -532,8 +560,7 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
     for (int i = 0; i < kRed; ++i) red[(wave * kRed + i) * 64 + lane] = acc[r][i];
     __syncthreads();
     const int p = pbase + 64 * r;
-    if (p < nh) {
-      const int f = wave;
+    for (int f = wave; f < NF && p < nh; f += kSynthWaves) {
       double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
 #pragma unroll
       for (int w = 0; w < kSynthWaves; ++w) {
@@ -547,7 +574,7 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
         vn = make_double2(-dm * vn.y, dm * vn.x);
         vs = make_double2(-dm * vs.y, dm * vs.x);
       }
-      double2* out = g.F + ((int64_t)(b * 4 + f) * (N + 1) + m) * nlat;
+      double2* out = (NF == 5 ? g.Fa : g.F) + ((int64_t)(b * NF + f) * (N + 1) + m) * nlat;
       out[p] = vn;
       const int psouth = nlat - 1 - p;
       if (psouth != p) out[psouth] = vs;
@@ -555,19 +582,19 @@ __device__ __forceinline__ void synthesis_adv_body(const GroupView& g, const Syn
   }
 }
 
-template <int R>
+template <int R, int NF>
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv(GroupView g, SynthInput in) {
-  synthesis_adv_body<R, false>(g, in, nullptr, nullptr);
+  synthesis_adv_body<R, NF, false>(g, in, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(kSynthThreads) void k_synthesis_adv_step(GroupView g, SynthInput in,
                                                                       NdfArgs a, NdfStepArgs st) {
-  synthesis_adv_body<1, true>(g, in, &a, &st);
+  synthesis_adv_body<1, 4, true>(g, in, &a, &st);
 }
 
-size_t synthesis_adv_lds_bytes(int N) {
-  const int arrays = 4 * (N + 1 + kOtfBatch);
-  const int red = kSynthWaves * 16 * 64 / 2;
+size_t synthesis_adv_lds_bytes(int N, int nf) {
+  const int arrays = nf * (N + 1 + kOtfBatch);
+  const int red = kSynthWaves * 4 * nf * 64 / 2;
   return sizeof(double2) * (size_t)(arrays > red ? arrays : red);
 }
 
@@ -599,7 +626,12 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
   dim3 block(kSynthThreads);
   const int ntile = (g.nh + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, ntile), g.nb);
-  if (mode == SYNTH_ADJ)
+  if (mode == SYNTH_ADJ && g.nh < 256) {
+    // the derivative form with the fifth field (T255 adjoint: 14.5 us with the
+    // panel form, 12.0 us; 78 VGPRs against 144)
+    hipLaunchKernelGGL((k_synthesis_adv<1, 5>), grid, block, synthesis_adv_lds_bytes(g.N, 5), s,
+                       g, in);
+  } else if (mode == SYNTH_ADJ)
     hipLaunchKernelGGL((k_synthesis<double, 5>), grid, block,
                        synthesis_lds_bytes(g.N, 5), s, g, in, mode);
   else if (g.precision == NSE_PREC_FP32) {
@@ -610,7 +642,8 @@ hipError_t launch_synthesis(const GroupView& g, const SynthInput& in, int mode, 
     // derivative-on-Legendre form reads three values per degree instead of five
     // (T255: 14.2 -> 13.8 us); with two or three latitudes per lane the panel
     // form's fewer FMAs per latitude win (T511: 38.6 us against 44.4 us)
-    hipLaunchKernelGGL(k_synthesis_adv<1>, grid, block, synthesis_adv_lds_bytes(g.N), s, g, in);
+    hipLaunchKernelGGL((k_synthesis_adv<1, 4>), grid, block, synthesis_adv_lds_bytes(g.N, 4), s, g,
+                       in);
   } else {
     return launch_synthesis_otf4<double>(g, in, mode, s);
   }
@@ -631,7 +664,7 @@ hipError_t launch_synthesis_step(const GroupView& g, const SynthInput& in, const
   if (!synthesis_takes_step(g)) return hipErrorInvalidValue;
   const int ntile = (g.nh + 63) / 64;
   dim3 grid(xcd_grid((g.N + 1) * ntile, ntile), g.nb);
-  const size_t lds = synthesis_adv_lds_bytes(g.N) + sizeof(NdfCtl) + 6 * sizeof(double);
+  const size_t lds = synthesis_adv_lds_bytes(g.N, 4) + sizeof(NdfCtl) + 6 * sizeof(double);
   hipLaunchKernelGGL(k_synthesis_adv_step, grid, dim3(kSynthThreads), lds, s, g, in, a, st);
   return hipGetLastError();
 }
