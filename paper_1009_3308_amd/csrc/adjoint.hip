@@ -33,8 +33,9 @@ size_t synthesis_adjoint_lds_bytes(int nh) {
 
 // One workgroup of four waves per (order m, tile of 64 degrees k < N+2-m,
 // member); one thread per degree, each wave summing a quarter of the northern
-// latitudes of T2[m][tile][p][64]. Orders are taken in XCD-local chunks of four
-// neighbouring m so that the strided reads of Fbar[lat][m] share L2 lines.
+// latitudes of T2[m][tile][p][64]. The cotangents of one order, Fbar[b][f][m][:],
+// are contiguous over latitude, so the fold reads them coalesced; orders are
+// taken in XCD-local chunks of four neighbouring m.
 __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) {
   const int N = g.N, nh = g.nh, nlat = g.nlat;
   const int ntile = (N + 2 + 63) / 64;
@@ -46,14 +47,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) 
   const int b = blockIdx.y;
   extern __shared__ double2 fsh[];  // [f][parity][nh]
   const int64_t fstride = (int64_t)(N + 1) * nlat;
-  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + m;  // Fbar[b][f][lat][m]
+  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)m * nlat;  // Fbar[b][f][m][lat]
   for (int i = threadIdx.x; i < 4 * nh; i += blockDim.x) {
     const int f = i / nh, p = i - f * nh;
     const int ps = nlat - 1 - p;
-    const double2 gn = Gb[f * fstride + (int64_t)p * (N + 1)];
+    const double2 gn = Gb[f * fstride + p];
     double2 we = gn, wo = make_double2(0.0, 0.0);
     if (ps != p) {
-      const double2 gs = Gb[f * fstride + (int64_t)ps * (N + 1)];
+      const double2 gs = Gb[f * fstride + ps];
       we = make_double2(gn.x + gs.x, gn.y + gs.y);
       wo = make_double2(gn.x - gs.x, gn.y - gs.y);
     }
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint_otf(GroupView
   // the cotangents of the four fields at every latitude pair (4 nh <= 256 R items,
   // R per thread), all requested before the first LDS write
   const int64_t fstride = (int64_t)(N + 1) * nlat;
-  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + m;  // Fbar[b][f][lat][m]
+  const double2* Gb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)m * nlat;  // Fbar[b][f][m][lat]
   double2 gn[R], gs[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -214,8 +215,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint_otf(GroupView
     if (idx < 4 * nh) {
       const int f = idx / nh, p = idx - f * nh;
       const int ps = nlat - 1 - p;
-      gn[i] = Gb[f * fstride + (int64_t)p * (N + 1)];
-      if (ps != p) gs[i] = Gb[f * fstride + (int64_t)ps * (N + 1)];
+      gn[i] = Gb[f * fstride + p];
+      if (ps != p) gs[i] = Gb[f * fstride + ps];
     }
   }
   // recurrence pairs (a(l,m), a(l,m) / a(l-1,m)) of the tile's degrees k = 2 .. L - 1;

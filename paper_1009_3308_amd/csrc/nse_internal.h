@@ -81,7 +81,7 @@ struct GroupView {
   const double2* rec_g;     // same slots: ((2l+1) e(l), lambda_l^(-1/2)), see rec_slot
   double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
   double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
-  double2* Fbar;            // adjoint: [nb][4][nlat][N+1] cotangents of the field spectra
+  double2* Fbar;            // adjoint: [nb][4][N+1][nlat] cotangents of the field spectra
   double2* Pbar;            // adjoint: [nb][N+1][N+2][4] cotangents of the panels
   double2* W;               // [nb][N+1][nlat] weighted ring spectra (analysis input),
                             // latitude fastest so the analysis reads them coalesced

@@ -790,7 +790,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
   __syncthreads();
   // unpack two real transforms per array, Z_k at row 3 a + k mod 3, k / 3:
   // A_m = (Z_m + conj Z_{M-m}) / 2, B_m = (Z_m - conj Z_{M-m}) / (2 i); times 2 for m >= 1
-  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + lat;  // Fbar[b][f][m][lat]
   for (int m = threadIdx.x; m <= N; m += NT) {
     const double sc = (m == 0) ? 0.5 : 1.0;
     const int mc = m == 0 ? 0 : M - m;
@@ -798,8 +798,8 @@ __global__ __launch_bounds__(NT) void k_ring_adj_nl(GroupView g) {
     for (int arr = 0; arr < 2; ++arr) {
       const double2 zm = lds[(3 * arr + m % 3) * PS + pad(m / 3)];
       const double2 zc = lds[(3 * arr + mc % 3) * PS + pad(mc / 3)];
-      Fb[(int64_t)(2 * arr) * fstride + m] = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
-      Fb[(int64_t)(2 * arr + 1) * fstride + m] = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
+      Fb[(int64_t)(2 * arr) * fstride + (int64_t)m * nlat] = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
+      Fb[(int64_t)(2 * arr + 1) * fstride + (int64_t)m * nlat] = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
     }
   }
 }
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_ring(GroupView g, FftPlan plan, int mode
 //   gbar0 = qbar g2 / s^2, gbar2 = qbar g0 / s^2, gbar1 = -qbar g3 / s^2, gbar3 = -qbar g1 / s^2
 // and the cotangents of the field spectra (the c2r of the synthesis)^T:
 //   Gbar_0 = sum_j gbar_j,  Gbar_m = 2 sum_j gbar_j e^{-i m phi_j}  (m >= 1),
-// written to Fbar[b][f][lat][m]. c_lat = (2 pi / M) w_p.
+// written to Fbar[b][f][m][lat]. c_lat = (2 pi / M) w_p.
 template <int MAXM, int NT, int CM>
 __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   constexpr int PTS = (MAXM + NT - 1) / NT;
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
   fft_any<2, MAXM, NT, CM>(A0, A1, plan, M, tw, -1.0);
   // unpack two real transforms per array: z = a + i b ->
   // A_m = (Z_m + conj Z_{M-m}) / 2, B_m = (Z_m - conj Z_{M-m}) / (2 i); times 2 for m >= 1
-  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + lat;  // Fbar[b][f][m][lat]
   for (int m = threadIdx.x; m <= N; m += blockDim.x) {
     const double sc = (m == 0) ? 0.5 : 1.0;
 #pragma unroll
@@ -995,8 +995,8 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
       const double2 zc = X[pad((M - m) % M)];
       const double2 ga = make_double2(sc * (zm.x + zc.x), sc * (zm.y - zc.y));
       const double2 gb = make_double2(sc * (zm.y + zc.y), -sc * (zm.x - zc.x));
-      Fb[(int64_t)(arr ? 2 : 0) * fstride + m] = ga;
-      Fb[(int64_t)(arr ? 3 : 1) * fstride + m] = gb;
+      Fb[(int64_t)(arr ? 2 : 0) * fstride + (int64_t)m * nlat] = ga;
+      Fb[(int64_t)(arr ? 3 : 1) * fstride + (int64_t)m * nlat] = gb;
     }
   }
 }
@@ -1005,7 +1005,7 @@ __global__ __launch_bounds__(NT) void k_ring_adj(GroupView g, FftPlan plan) {
 // per ring, the real transforms Ut_m = sum_j u_theta e^{-i m phi_j} and
 // Up_m = sum_j u_phi e^{-i m phi_j} (one complex FFT of u_theta + i u_phi),
 // scaled by c = (2 pi / M) w_p / sin(theta_p) and written to
-// Fbar[b][f][lat][m] as (c Ut, -c Up, 0, 0). The latitude sums and the degree
+// Fbar[b][f][m][lat] as (c Ut, -c Up, 0, 0). The latitude sums and the degree
 // coupling of d/dtheta are done by the unweighted analysis and the prologue
 // transpose, since conj(Z[l,m]) = lambda^(-1/2) (-i m Pbar / sin, -dPbar/dtheta) e^{-i m phi}
 // and sin(theta) dPbar/dtheta couples degrees l - 1 and l + 1.
@@ -1030,15 +1030,16 @@ __global__ __launch_bounds__(NT) void k_ring_project(GroupView g, FftPlan plan,
   const double x = g.mu[p];
   const double c = (6.283185307179586477 / M) * g.w[p] / sqrt((1.0 - x) * (1.0 + x));
   const int64_t fstride = (int64_t)(N + 1) * nlat;
-  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + (int64_t)lat * (N + 1);
+  double2* Fb = g.Fbar + (int64_t)b * 4 * fstride + lat;  // Fbar[b][f][m][lat]
   for (int m = threadIdx.x; m <= N; m += blockDim.x) {
     const double2 zm = A0[pad(m)];
     const double2 zc = A0[pad((M - m) % M)];
     const double h = 0.5 * c;
-    Fb[m] = make_double2(h * (zm.x + zc.x), h * (zm.y - zc.y));
-    Fb[fstride + m] = make_double2(-h * (zm.y + zc.y), h * (zm.x - zc.x));
-    Fb[2 * fstride + m] = make_double2(0.0, 0.0);
-    Fb[3 * fstride + m] = make_double2(0.0, 0.0);
+    const int64_t mo = (int64_t)m * nlat;
+    Fb[mo] = make_double2(h * (zm.x + zc.x), h * (zm.y - zc.y));
+    Fb[fstride + mo] = make_double2(-h * (zm.y + zc.y), h * (zm.x - zc.x));
+    Fb[2 * fstride + mo] = make_double2(0.0, 0.0);
+    Fb[3 * fstride + mo] = make_double2(0.0, 0.0);
   }
 }
 
