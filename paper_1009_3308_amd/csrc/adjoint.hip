@@ -15,6 +15,7 @@
 //   zeta_bar[j] = -i m f3_bar[j] + cm(j+1) f2_bar[j+1] - cp(j-1) f2_bar[j-1],
 //   alpha_bar[j] = lambda^(-1/2) psi_bar[j] + lambda^(1/2) zeta_bar[j],
 // zero at l = 0 and real at m = 0 (those inputs are fixed to zero).
+#include "adjoint_device.h"
 #include "lane_ops.h"
 #include "spectral_ops.h"
 
@@ -118,35 +119,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_synthesis_adjoint(GroupView g) 
     }
     out[f] = make_double2(sx, sy);
   }
-}
-
-// alpha_bar at degree l = m + k of member b from the panel cotangents of
-// order m (P = Pbar[b][m][k][f]): the transposed panel recurrences above.
-__device__ inline double2 alpha_bar_at(const GroupView& g, const double2* P, int m, int k) {
-  const int N = g.N, L = N + 2 - m, l = m + k;
-  if (l < 1) return make_double2(0.0, 0.0);
-  const double dm = (double)m;
-  auto e_of = [&](int ll) -> double {
-    return (ll > m) ? sqrt(((double)ll * ll - dm * dm) / (4.0 * (double)ll * ll - 1.0)) : 0.0;
-  };
-  double2 psib = make_double2(dm * P[4 * k + 0].y, -dm * P[4 * k + 0].x);  // -i m f0_bar
-  double2 zetb = make_double2(dm * P[4 * k + 3].y, -dm * P[4 * k + 3].x);  // -i m f3_bar
-  if (k + 1 < L) {
-    const double cmn = (double)l * e_of(l + 1);  // cm(k+1)
-    psib.x += cmn * P[4 * (k + 1) + 1].x;
-    psib.y += cmn * P[4 * (k + 1) + 1].y;
-    zetb.x += cmn * P[4 * (k + 1) + 2].x;
-    zetb.y += cmn * P[4 * (k + 1) + 2].y;
-  }
-  if (k >= 1) {
-    const double cpp = (double)(l + 1) * e_of(l);  // cp(k-1)
-    psib.x -= cpp * P[4 * (k - 1) + 1].x;
-    psib.y -= cpp * P[4 * (k - 1) + 1].y;
-    zetb.x -= cpp * P[4 * (k - 1) + 2].x;
-    zetb.y -= cpp * P[4 * (k - 1) + 2].y;
-  }
-  const double sq = sqrt((double)l * (l + 1));
-  return make_double2(psib.x / sq + zetb.x * sq, m == 0 ? 0.0 : psib.y / sq + zetb.y * sq);
 }
 
 // One workgroup per (order m, member); one thread per degree l = m..N.
@@ -303,52 +275,22 @@ hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream
   return hipGetLastError();
 }
 
-// The adjoint of one step after the nonlinear adjoint at the predictor, one
-// thread per (order m, degree k), in place over hist_bar: with
-// r = hbar_out[0] / (c_0 + h nu lambda) (zero at l = 0, real at m = 0) and
-// alpha_bar the predictor cotangent from the panel cotangents,
-//   hbar_in[j] = hbar_out[j+1] - c_{j+1} r + pi_j alpha_bar,   j = 0 .. depth-1.
-// (The cotangent of the nonlinear term, n_bar = -h r, was formed inside the
-// five-field synthesis from the same hbar_out[0].)
-__global__ __launch_bounds__(256) void k_prep_step_adjoint(GroupView g, AnalOutput st,
-                                                           SynthInput pred, double2* hist_bar) {
+// The history update that ends the adjoint of one step (StepAdjointArgs), one
+// thread per (order m, degree k), in place over hist_bar (each thread reads its
+// coefficient's cotangents before it writes them). The cotangent of the
+// nonlinear term, n_bar = -h r, was formed inside the five-field synthesis
+// from the same hbar_out[0].
+__global__ __launch_bounds__(256) void k_prep_step_adjoint(GroupView g, StepAdjointArgs a) {
   const int N = g.N;
   const int m = blockIdx.x, b = blockIdx.z;
   const int k = blockIdx.y * blockDim.x + threadIdx.x;
   if (k > N - m) return;
-  const int l = m + k;
-  const double2* P = g.Pbar + ((int64_t)b * (N + 1) + m) * (N + 2) * 4;
-  const double2 ab = alpha_bar_at(g, P, m, k);
-  const int64_t slot = g.off[b] + coeff_offset(N, m) + k;
-  const double lam = (double)l * (l + 1);
-  const double denom = st.c[0] + st.h * g.nu[b] * lam;
-  double2 r = hist_bar[slot];
-  r = make_double2(r.x / denom, r.y / denom);
-  if (l == 0) r = make_double2(0.0, 0.0);
-  if (m == 0) r.y = 0.0;
-  double2 hb[kMaxStepCoef];
-#pragma unroll
-  for (int j = 0; j < kMaxStepCoef; ++j) {
-    hb[j] = make_double2(0.0, 0.0);
-    if (j + 1 < st.depth) hb[j] = hist_bar[(int64_t)(j + 1) * st.state_count + slot];
-    if (j + 1 < st.ncoef) {
-      hb[j].x -= st.c[j + 1] * r.x;
-      hb[j].y -= st.c[j + 1] * r.y;
-    }
-    if (j < pred.nsrc) {
-      hb[j].x += pred.coef[j] * ab.x;
-      hb[j].y += pred.coef[j] * ab.y;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kMaxStepCoef; ++j)
-    if (j < st.depth) hist_bar[(int64_t)j * st.state_count + slot] = hb[j];
+  step_adjoint_store(g, a, b, m, k);
 }
 
-hipError_t launch_prep_step_adjoint(const GroupView& g, const AnalOutput& st,
-                                    const SynthInput& pred, double2* hist_bar, hipStream_t s) {
+hipError_t launch_prep_step_adjoint(const GroupView& g, const StepAdjointArgs& a, hipStream_t s) {
   dim3 grid(g.N + 1, (g.N + 1 + 255) / 256, g.nb);
-  hipLaunchKernelGGL(k_prep_step_adjoint, grid, dim3(256), 0, s, g, st, pred, hist_bar);
+  hipLaunchKernelGGL(k_prep_step_adjoint, grid, dim3(256), 0, s, g, a);
   return hipGetLastError();
 }
 

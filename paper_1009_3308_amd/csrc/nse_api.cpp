@@ -44,7 +44,7 @@ struct Group {
   double *d_mu = nullptr, *d_w = nullptr, *d_T1 = nullptr, *d_T2 = nullptr;
   float *d_T1f = nullptr, *d_T2f = nullptr;
   int64_t* d_t2off = nullptr;
-  double2 *d_rec_a = nullptr, *d_rec_g = nullptr;  // recurrence coefficients (rec_slot)
+  double2 *d_rec_a = nullptr, *d_rec_g = nullptr, *d_rec_p = nullptr;  // recurrence coefficients (rec_slot)
   uint64_t* d_lps = nullptr;      // split-bf16 synthesis panels (BF16X3 groups)
   int64_t* d_lpsoff = nullptr;
   int64_t lps_stride = 0;         // per member, 8-byte units
@@ -73,6 +73,7 @@ struct Group {
     g.t2off = d_t2off;
     g.rec_a = d_rec_a;
     g.rec_g = d_rec_g;
+    g.rec_p = d_rec_p;
     g.F = d_F;
     g.Fa = d_Fa;
     g.Fbar = d_Fbar;
@@ -261,6 +262,7 @@ void free_group(Group& g) {
   (void)hipFree(g.d_t2off);
   (void)hipFree(g.d_rec_a);
   (void)hipFree(g.d_rec_g);
+  (void)hipFree(g.d_rec_p);
   (void)hipFree(g.d_lps);
   (void)hipFree(g.d_lpsoff);
   (void)hipFree(g.d_F);
@@ -316,7 +318,7 @@ nse_status build_group(nse_ctx* c, Group& g) {
   {
     // recurrence coefficients, in long double and rounded once
     const int64_t nrec = (int64_t)(g.N + 2) * (g.N + 3) / 2;
-    std::vector<double2> ra(nrec), rg(nrec);
+    std::vector<double2> ra(nrec), rg(nrec), rp(nrec);
     for (int m = 0; m <= g.N; ++m) {
       const long double lm = m;
       auto a_of = [&](int l) -> long double {
@@ -331,12 +333,17 @@ nse_status build_group(nse_ctx* c, Group& g) {
         const long double rs = (l > 0) ? 1.0L / std::sqrt((long double)l * (l + 1)) : 0.0L;
         ra[sl] = make_double2((double)al, (double)ratio);
         rg[sl] = make_double2((double)gl, (double)rs);
+        const long double en = (l + 1 <= g.N + 1) ? 1.0L / a_of(l + 1) : 0.0L;  // e(l+1)
+        const long double el = (l > m) ? 1.0L / al : 0.0L;                      // e(l)
+        rp[sl] = make_double2((double)((long double)l * en), (double)((l + 1.0L) * el));
       }
     }
     NSE_HIP(c, dalloc(&g.d_rec_a, nrec));
     NSE_HIP(c, dalloc(&g.d_rec_g, nrec));
+    NSE_HIP(c, dalloc(&g.d_rec_p, nrec));
     NSE_HIP(c, hipMemcpy(g.d_rec_a, ra.data(), sizeof(double2) * nrec, hipMemcpyHostToDevice));
     NSE_HIP(c, hipMemcpy(g.d_rec_g, rg.data(), sizeof(double2) * nrec, hipMemcpyHostToDevice));
+    NSE_HIP(c, hipMemcpy(g.d_rec_p, rp.data(), sizeof(double2) * nrec, hipMemcpyHostToDevice));
   }
   if (c->params.precision == NSE_PREC_BF16X3) {
     // FP32 copies of the tables, split into bf16 pieces in registers (the FP64
@@ -1471,36 +1478,44 @@ nse_status nse_nonlinear_adjoint_noalloc(nse_ctx* ctx, const double* alpha, cons
 extern "C++" {
 namespace {
 
-// The adjoint of step `step` (one fixed-point sweep) at history `hist`,
-// accumulating into hist_bar.
-nse_status enqueue_step_adjoint(nse_ctx* ctx, const double2* hist, int64_t step,
-                                       double2* hb) {
-  std::vector<double> cc, pi;
-  step_scheme(ctx->params.order, step, cc, pi);
-  AnalOutput st{};
-  st.state_count = ctx->state_count;
-  st.depth = ctx->params.order + 1;
-  st.ncoef = (int)cc.size();
-  for (int j = 0; j < st.ncoef; ++j) st.c[j] = cc[j];
-  st.h = ctx->params.dt;
-  SynthInput pred{};
-  pred.nsrc = (int)pi.size();
-  for (int i = 0; i < pred.nsrc; ++i) {
-    pred.src[i] = hist + (int64_t)i * ctx->state_count;
-    pred.coef[i] = pi[i];
-  }
-  pred.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
-  SynthInput in = pred;
-  in.adj = hb;  // hbar_out[0]; n_bar is formed inside the five-field synthesis
-  in.adj_step = 1;
-  in.adj_c0 = cc[0];
-  in.adj_h = ctx->params.dt;
-  for (auto& g : ctx->groups) {
-    const GroupView v = g.view();
-    NSE_HIP(ctx, launch_synthesis(v, in, SYNTH_ADJ, ctx->stream));
-    NSE_HIP(ctx, launch_ring_adjoint(v, g.plan, ctx->stream));
-    NSE_HIP(ctx, launch_synthesis_adjoint(v, ctx->stream));
-    NSE_HIP(ctx, launch_prep_step_adjoint(v, st, pred, hb, ctx->stream));
+// The adjoints (one fixed-point sweep each) of steps i_hi - 1 down to i_lo of
+// a trajectory buffer, step i at history tr + (n - i) S and absolute index
+// step0 + i, accumulating into hb.
+nse_status enqueue_adjoint_sweep(nse_ctx* ctx, const double2* tr, int64_t n, int64_t step0,
+                                 int64_t i_hi, int64_t i_lo, double2* hb) {
+  const int64_t S = ctx->state_count;
+  for (int64_t i = i_hi - 1; i >= i_lo; --i) {
+    std::vector<double> cc, pi;
+    step_scheme(ctx->params.order, step0 + i, cc, pi);
+    const double2* hist = tr + (n - i) * S;
+    SynthInput in{};
+    in.nsrc = (int)pi.size();
+    for (int j = 0; j < in.nsrc; ++j) {
+      in.src[j] = hist + (int64_t)j * S;
+      in.coef[j] = pi[j];
+    }
+    in.coriolis = 2.0 * ctx->params.omega * std::sqrt(4.0 * kPi / 3.0);
+    in.adj = hb;      // hbar_out[0]; n_bar is formed inside the five-field synthesis
+    in.adj_step = 1;
+    in.adj_c0 = cc[0];
+    in.adj_h = ctx->params.dt;
+    StepAdjointArgs a{};
+    a.hin = hb;
+    a.hout = hb;
+    a.state_count = S;
+    a.depth = ctx->params.order + 1;
+    a.ncoef = (int)cc.size();
+    for (int j = 0; j < a.ncoef; ++j) a.c[j] = cc[j];
+    a.npi = (int)pi.size();
+    for (int j = 0; j < a.npi; ++j) a.pi[j] = pi[j];
+    a.h = ctx->params.dt;
+    for (auto& g : ctx->groups) {
+      const GroupView v = g.view();
+      NSE_HIP(ctx, launch_synthesis(v, in, SYNTH_ADJ, ctx->stream));
+      NSE_HIP(ctx, launch_ring_adjoint(v, g.plan, ctx->stream));
+      NSE_HIP(ctx, launch_synthesis_adjoint(v, ctx->stream));
+      NSE_HIP(ctx, launch_prep_step_adjoint(v, a, ctx->stream));
+    }
   }
   return NSE_OK;
 }
@@ -1578,7 +1593,7 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forc
     return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
   nse_status s = ensure_adjoint_buffers(ctx);
   if (s != NSE_OK) return s;
-  return enqueue_step_adjoint(ctx, (const double2*)hist, step, (double2*)hist_bar);
+  return enqueue_adjoint_sweep(ctx, (const double2*)hist, 0, step, 1, 0, (double2*)hist_bar);
 }
 
 nse_status nse_step_trajectory(nse_ctx* ctx, double* traj, const double* forcing, int64_t step0,
@@ -1632,21 +1647,13 @@ nse_status nse_step_adjoint_trajectory(nse_ctx* ctx, const double* traj, const d
   // steps n - 1 .. 0; those with fixed coefficients (step0 + i > p) first
   const int64_t ifix = std::max<int64_t>(0, std::min<int64_t>(n, p + 1 - step0));
   const auto body = [&]() -> nse_status {
-    for (int64_t i = n - 1; i >= ifix; --i) {
-      nse_status st = enqueue_step_adjoint(ctx, tr + (n - i) * S, step0 + i, hb);
-      if (st != NSE_OK) return st;
-    }
-    return NSE_OK;
+    return enqueue_adjoint_sweep(ctx, tr, n, step0, n, ifix, hb);
   };
   const bool graph =
       (ctx->params.flags & NSE_FLAG_GRAPH) && !ctx->profiling && n - ifix >= 2;
   s = graph ? run_sequence_graph(ctx, 2, traj, hist_bar, forcing, n, ifix, n, body) : body();
   if (s != NSE_OK) return s;
-  for (int64_t i = ifix - 1; i >= 0; --i) {
-    s = enqueue_step_adjoint(ctx, tr + (n - i) * S, step0 + i, hb);
-    if (s != NSE_OK) return s;
-  }
-  return NSE_OK;
+  return enqueue_adjoint_sweep(ctx, tr, n, step0, ifix, 0, hb);
 }
 
 nse_status nse_synthesize(nse_ctx* ctx, const double* alpha, double* grid_out) {

@@ -47,6 +47,8 @@ __host__ __device__ inline int64_t coeff_offset(int N, int m) {
 // computed once per group on the host, for l = m .. N+1 at rec_slot(N, l, m):
 //   rec_a = (a(l,m), a(l,m) / a(l-1,m)),  a(l,m) = sqrt((4 l^2 - 1) / (l^2 - m^2)),
 //   rec_g = ((2l+1) e(l), lambda_l^(-1/2)),  e(l) = 1 / a(l,m),
+//   rec_p = (l e(l+1), (l+1) e(l))  (the coefficients of the transposed panel
+//           recurrences of the adjoint; l e(l+1) = 0 at l = N+1),
 // with a(m,m) = e(m) = 0, the ratio 0 for l <= m+1 (it multiplies Pbar[m-1,m] = 0)
 // and lambda^(-1/2) = 0 at l = 0.
 __host__ __device__ inline int64_t rec_slot(int N, int l, int m) {
@@ -79,6 +81,7 @@ struct GroupView {
   const int64_t* t2off;     // [N+2] start of order m in T2 (element units)
   const double2* rec_a;     // [(N+2)(N+3)/2] (a(l,m), a(l,m) / a(l-1,m)), slot rec_slot(N, l, m)
   const double2* rec_g;     // same slots: ((2l+1) e(l), lambda_l^(-1/2)), see rec_slot
+  const double2* rec_p;     // same slots: (l e(l+1), (l+1) e(l)), see rec_slot
   double2* F;               // [nb][4][N+1][nlat] Fourier coefficients of grid fields
   double2* Fa;              // adjoint: [nb][5][N+1][nlat] (4 forward fields + adjoint input)
   double2* Fbar;            // adjoint: [nb][4][N+1][nlat] cotangents of the field spectra
@@ -103,6 +106,24 @@ struct FftPlan {
   int nstages;
   int radix[kMaxRadices];
   int ns_log2[kMaxRadices];  // log2 of the stride Ns before each stage, -1 if not a power of 2
+};
+
+// The history update that ends the adjoint of one NDF step (eq. (ode_disc)
+// transposed), from the panel cotangents Pbar of its nonlinear adjoint:
+//   r = hin[0] / (c_0 + h nu lambda)   (zero at l = 0, real at m = 0),
+//   hout[j] = hin[j+1] - c_{j+1} r + pi_j alpha_bar,   j = 0 .. depth-1,
+// with alpha_bar the predictor cotangent (the transposed panel recurrences) and
+// pi_j the predictor's weights.
+struct StepAdjointArgs {
+  const double2* hin;  // [depth][state]
+  double2* hout;       // [depth][state]; may equal hin
+  int64_t state_count;
+  int depth;           // order + 1
+  int ncoef;           // c_0 .. c_{ncoef-1}
+  int npi;             // pi_0 .. pi_{npi-1}
+  double c[kMaxStepCoef];
+  double pi[kMaxSources];
+  double h;
 };
 
 // Input of the synthesis: sum_i coef[i] * src[i] (predictor or plain state).
@@ -218,8 +239,7 @@ hipError_t launch_ring_project(const GroupView& g, const FftPlan& plan, const do
                                hipStream_t s);
 hipError_t launch_synthesis_adjoint(const GroupView& g, hipStream_t s);
 hipError_t launch_prep_adjoint(const GroupView& g, double2* alpha_bar, hipStream_t s);
-hipError_t launch_prep_step_adjoint(const GroupView& g, const AnalOutput& st,
-                                    const SynthInput& pred, double2* hist_bar, hipStream_t s);
+hipError_t launch_prep_step_adjoint(const GroupView& g, const StepAdjointArgs& a, hipStream_t s);
 hipError_t launch_synthesis_mb(const GroupView& g, const SynthInput& in, int B, hipStream_t s);
 hipError_t launch_analysis_mb(const GroupView& g, const AnalOutput& out, int B, hipStream_t s);
 hipError_t launch_synthesis_lp(const GroupView& g, const SynthInput& in, int mode, int prec,
