@@ -5,8 +5,9 @@
 // truncation groups on forked streams, autotuned member blocks, step graphs
 // captured and replayed, the graph cache filled past its bound and evicted),
 // many single-member contexts sharing one stream, the nonlinear adjoint on
-// allocated and on static scratch, an adaptive integration, and destruction of
-// everything. Any host memory error aborts with an ASan report; the last line
+// allocated and on static scratch, a trajectory and its step adjoints (eager and
+// from captured graphs), one step adjoint, the grid synthesis and the
+// projection, an adaptive integration, and destruction of everything. Any host memory error aborts with an ASan report; the last line
 // printed on success is "asan driver: ok".
 #include <hip/hip_runtime.h>
 
@@ -127,6 +128,34 @@ static void gpu_paths() {
   double* out = device_state(n1, 0.0);
   EXPECT(nse_nonlinear_adjoint(a, al, nb, out) == NSE_OK);
   EXPECT(nse_nonlinear_adjoint_noalloc(a, al, nb, out) == NSE_OK);
+
+  // trajectory buffers and step adjoints, eager here and from captured graphs
+  // in a second context (each call twice: capture, then replay)
+  const int32_t nsteps = 25, depth = q.order + 1;
+  double* traj = device_state((int64_t)(nsteps + depth) * n1, 1e-3);
+  double* hbar = device_state((int64_t)depth * n1, 1.0);
+  EXPECT(nse_step_trajectory(a, traj, nullptr, 0, nsteps) == NSE_OK);
+  EXPECT(nse_step_adjoint_trajectory(a, traj, nullptr, 0, nsteps, hbar) == NSE_OK);
+  EXPECT(nse_step_adjoint(a, traj + 2 * n1 * 3, nullptr, 7, hbar) == NSE_OK);
+  EXPECT(nse_step_adjoint_trajectory(a, traj, nullptr, 0, nsteps, traj) == NSE_ERR_ARG);
+  nse_params qg = params(NSE_FLAG_GRAPH);
+  nse_ctx* ag = nullptr;
+  EXPECT(nse_sphere_init(m1, 1, &qg, st, &ag) == NSE_OK);
+  for (int rep = 0; rep < 2; ++rep) {
+    EXPECT(nse_step_trajectory(ag, traj, nullptr, 3, nsteps) == NSE_OK);
+    EXPECT(nse_step_adjoint_trajectory(ag, traj, nullptr, 3, nsteps, hbar) == NSE_OK);
+  }
+  EXPECT(nse_sync(ag) == NSE_OK);
+  EXPECT(nse_sphere_destroy(ag) == NSE_OK);
+  // grid synthesis and the projection back onto the basis
+  int32_t nlat = 0;
+  EXPECT(nse_member_grid(a, 0, &nlat, nullptr, nullptr) == NSE_OK);
+  double* grid = nullptr;
+  EXPECT(hipMalloc((void**)&grid, sizeof(double) * 3 * nlat * 2 * nlat) == hipSuccess);
+  EXPECT(nse_synthesize(a, al, grid) == NSE_OK);
+  EXPECT(nse_analyze_velocity(a, grid, out) == NSE_OK);
+  EXPECT(nse_sync(a) == NSE_OK);
+  std::printf("asan driver: trajectory, step adjoints and projection ok\n");
   nse_adaptive_params ap{};
   ap.rtol = 1e-3;
   ap.atol = 1e-6;
@@ -148,6 +177,9 @@ static void gpu_paths() {
   (void)hipFree(al);
   (void)hipFree(nb);
   (void)hipFree(out);
+  (void)hipFree(traj);
+  (void)hipFree(hbar);
+  (void)hipFree(grid);
   (void)hipStreamDestroy(st);
 }
 
