@@ -18,6 +18,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -32,21 +33,36 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # its two HIP events, which spreads the event overhead (about 2.5 us) thin
 PROFILE_REPEAT = 10
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-# sources each kernel is built from: measured traffic is used only while these
-# are unchanged since the counters were taken
-KERNEL_SOURCES = {
-    "synthesis": ["paper_1009_3308_amd/csrc/synthesis.hip",
-                  "paper_1009_3308_amd/csrc/spectral_ops.h",
-                  "paper_1009_3308_amd/csrc/ndf_control.h",
-                  "paper_1009_3308_amd/csrc/nse_internal.h"],
-    "ring": ["paper_1009_3308_amd/csrc/ring_fft.hip",
-             "paper_1009_3308_amd/csrc/nse_internal.h"],
-    "analysis": ["paper_1009_3308_amd/csrc/analysis.hip",
-                 "paper_1009_3308_amd/csrc/lane_ops.h",
-                 "paper_1009_3308_amd/csrc/spectral_ops.h",
-                 "paper_1009_3308_amd/csrc/ndf_control.h",
-                 "paper_1009_3308_amd/csrc/nse_internal.h"],
+# the source file of each kernel; measured traffic is used only while it and
+# every file it includes (its local #include "..." closure) are unchanged since
+# the counters were taken
+KERNEL_ROOTS = {
+    "synthesis": "paper_1009_3308_amd/csrc/synthesis.hip",
+    "ring": "paper_1009_3308_amd/csrc/ring_fft.hip",
+    "analysis": "paper_1009_3308_amd/csrc/analysis.hip",
 }
+INCLUDE_DIRS = ("paper_1009_3308_amd/csrc", "include")
+
+
+def kernel_sources(kernel):
+    """The kernel's source file and its local includes, in a fixed order."""
+    seen, todo = [], [KERNEL_ROOTS[kernel]]
+    while todo:
+        path = todo.pop(0)
+        if path in seen:
+            continue
+        seen.append(path)
+        with open(os.path.join(ROOT, path)) as f:
+            for line in f:
+                m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+                if not m:
+                    continue
+                for d in INCLUDE_DIRS:
+                    cand = os.path.join(d, m.group(1))
+                    if os.path.exists(os.path.join(ROOT, cand)):
+                        todo.append(cand)
+                        break
+    return seen
 
 
 def log(msg):
@@ -119,7 +135,7 @@ def kernel_roofline(kernel, N, nlat, avg_ms, abytes):
 
 def source_sha(kernel):
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES[kernel]:
+    for path in kernel_sources(kernel):
         with open(os.path.join(ROOT, path), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

@@ -1593,6 +1593,7 @@ nse_status nse_step_adjoint(nse_ctx* ctx, const double* hist, const double* forc
     return fail(ctx, NSE_ERR_UNSUPPORTED, "the step adjoint needs newton_iters == 1");
   nse_status s = ensure_adjoint_buffers(ctx);
   if (s != NSE_OK) return s;
+  // a sweep of one step (i = 0) over a buffer whose history slot n - i = 0 is hist
   return enqueue_adjoint_sweep(ctx, (const double2*)hist, 0, step, 1, 0, (double2*)hist_bar);
 }
 
